@@ -1,0 +1,213 @@
+/*
+ * rk.h -- C ABI of librk, an MI355X (gfx950) multi-pattern Rabin-Karp search.
+ *
+ * Problem (Shah & Oza, "Improved Parallel Rabin-Karp Algorithm Using CUDA",
+ * Sec. 1 and Sec. 3.1): find every occurrence of every pattern P_j in a text T.
+ * For each text window the library forms a polynomial hash, tests it against the
+ * set of pattern hashes and confirms a hit by comparing bytes, as the paper's
+ * sequential and GPU procedures do for one pattern.
+ *
+ *   hash(s[0..m)) = sum_{i<m} s[i] * d^(m-1-i)  (mod q),   bytes unsigned,
+ *
+ * with d = 256 and q = 2^61 - 1 fixed by this library (the paper's own hash is
+ * the shift-and-add case d = 2 with no modulus).  Results are exact: pattern j's
+ * result is the ascending list of every x in [0, n - m_j] with
+ * T[x .. x+m_j) == P_j, overlapping occurrences included, whatever hash
+ * collisions happen.
+ *
+ * Conventions for every call:
+ *   - No call throws or aborts; each returns an rk_status.  After a non-OK
+ *     status rk_ctx_last_error() describes it and outputs are undefined.
+ *   - "_dev" pointers are device memory of the context's GPU; "_host" pointers
+ *     are host memory.  The caller owns every buffer it passes; the library
+ *     never frees or modifies inputs and keeps no pointer to them after the call
+ *     returns, except where a call says otherwise (plans and servers keep the
+ *     device text pointers they are given until destroyed).
+ *   - Text device pointers must be 16-byte aligned (RK_EINVAL otherwise): the
+ *     scan reads whole aligned 16-byte blocks, so it never touches a block that
+ *     holds no text byte.
+ *   - rk_stream is a hipStream_t (NULL: the legacy default stream).  Work is
+ *     enqueued on it; calls that return a host-visible value synchronise it.
+ *   - A context is bound to one device and is not thread-safe; use one per
+ *     host thread.  The server object is the exception (see below).
+ *   - Pattern lengths: 1 <= m <= RK_MAX_M.  m = 0 is RK_EINVAL, m > RK_MAX_M is
+ *     RK_EUNSUPPORTED, m > n yields an empty list.  k = 0 is valid (no hits).
+ *   - Device faults and launch failures surface as RK_EDEVICE.
+ */
+#ifndef RK_H
+#define RK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RK_MAX_M 64u                 /* longest pattern the scan kernels accept */
+#define RK_MAX_PID ((1u << 24) - 1)  /* largest pattern id in one plan (k <= 2^24) */
+#define RK_MAX_N ((1ull << 40) - 1)  /* largest text length (positions are 40-bit) */
+
+typedef enum {
+  RK_OK = 0,
+  RK_EINVAL = -1,       /* bad argument: null pointer, m = 0, misaligned text, ... */
+  RK_ENOMEM = -2,       /* host or device allocation failed */
+  RK_EUNSUPPORTED = -3, /* valid but not supported: d or q other than 256 / 2^61-1, m > RK_MAX_M */
+  RK_EDEVICE = -4,      /* HIP runtime error or device fault */
+  RK_ENOSPACE = -5,     /* a caller buffer (scratch, work, output capacity) is too small */
+  RK_EBUSY = -6,        /* request not finished yet (server poll) */
+  RK_ECANCELED = -7     /* request canceled or its server shut down */
+} rk_status;
+
+/* Scan modes.  Both give identical results.
+ *   RK_MODE_EXACT : every window's d=256 / q=2^61-1 hash is rolled and tested
+ *                   against the pattern-hash set; equal hashes are byte-checked.
+ *   RK_MODE_SCREEN: every window first gets the paper's shift-and-add hash
+ *                   h <- (h << s) + c taken mod 2^32 (shift s in {1,2,4,8}
+ *                   chosen per pattern length, s = 1 being the paper's form);
+ *                   windows whose shift-add hash is in the set get the exact
+ *                   d=256 / q=2^61-1 hash, and equal exact hashes are
+ *                   byte-checked.  A true occurrence always passes both tests,
+ *                   so no occurrence is lost.
+ *   RK_MODE_AUTO  : RK_MODE_SCREEN. */
+typedef enum { RK_MODE_AUTO = 0, RK_MODE_EXACT = 1, RK_MODE_SCREEN = 2 } rk_mode;
+
+typedef void *rk_stream; /* hipStream_t */
+
+typedef struct rk_ctx rk_ctx;
+typedef struct rk_plan rk_plan;
+
+/* ------------------------------------------------------------------ context */
+
+/* Create a context on HIP device `device` for base d and modulus q.  Only
+ * d = 256 and q = 2^61 - 1 are supported (RK_EUNSUPPORTED otherwise); the
+ * arguments exist so that the hash parameters are explicit at the boundary.
+ * *out receives the context.  Makes `device` current on the calling thread. */
+rk_status rk_ctx_create(int device, uint64_t d, uint64_t q, rk_ctx **out);
+void rk_ctx_destroy(rk_ctx *ctx);
+/* Text of the last failure on this context ("" if none).  Owned by the context. */
+const char *rk_ctx_last_error(const rk_ctx *ctx);
+/* Static name of a status code. */
+const char *rk_status_string(rk_status s);
+
+/* Options (rk_ctx_set_option).  Values are read when a plan is created or a
+ * scan is launched. */
+typedef enum {
+  RK_OPT_SLAB_CAP = 1,  /* per-tile staging slots for hits (0 = default: tile bytes / 64).
+                           Tiles with more hits are rescanned by rk_collect. */
+  RK_OPT_TILE_CFG = 2,  /* scan geometry index into the built-in table (see rk_tile_cfg);
+                           -1 = autotuned / default */
+  RK_OPT_GRID = 3,      /* workgroups of the persistent scan (0 = default: 8 per CU) */
+  RK_OPT_PROFILE = 4,   /* 1: time every scan launch with HIP events (rk_ctx_profile) */
+  RK_OPT_QUEUE = 5      /* 1: scan pulls tiles from an atomic work queue; 0: static striding;
+                           -1 (default): queue for multi-instance plans only */
+} rk_option;
+rk_status rk_ctx_set_option(rk_ctx *ctx, int option, int64_t value);
+
+/* Scan geometry table entry i (0 <= i < rk_tile_cfg_count()): workgroup size,
+ * windows per thread, and tile bytes = wg * windows. */
+int rk_tile_cfg_count(void);
+rk_status rk_tile_cfg(int i, uint32_t *wg, uint32_t *windows_per_thread, uint32_t *tile_bytes);
+
+/* Accumulated device time of scan launches since profiling was switched on.
+ * kernel: 0 = scan (count pass), 1 = rescan of overflowed tiles, 2 = collect
+ * (compaction + sort), 3 = all.  Synchronises the context's device. */
+rk_status rk_ctx_profile(rk_ctx *ctx, int kernel, uint64_t *launches, double *total_ms);
+rk_status rk_ctx_profile_reset(rk_ctx *ctx);
+
+/* hash(s[0..m)) in [0, q), computed on the host with the library's own
+ * arithmetic (Sec. 3.1: the pattern hash hx is computed once on the host). */
+rk_status rk_hash(const rk_ctx *ctx, const uint8_t *s_host, uint64_t m, uint64_t *out);
+
+/* -------------------------------------------------------------------- plans */
+
+/* A plan holds preprocessed patterns (the paper computes hx once on the host and
+ * passes it to the kernel, Sec. 3.1): lengths bucketed, pattern hashes and
+ * screen hashes computed, per-bucket hash tables built and uploaded.
+ * Pattern j = bytes_host[offsets_host[j] .. offsets_host[j+1]), j < k; the
+ * host arrays are copied and may be freed after the call.  mode: rk_mode. */
+rk_status rk_plan_create(rk_ctx *ctx, const uint8_t *bytes_host, const uint64_t *offsets_host,
+                         uint32_t k, int mode, rk_plan **out);
+void rk_plan_destroy(rk_plan *plan);
+/* Number of patterns (for a batch plan: the sum over instances). */
+uint32_t rk_plan_patterns(const rk_plan *plan);
+
+/* Bytes of device scratch that rk_count / rk_collect need for a text of n
+ * bytes (a function of n, the plan and RK_OPT_SLAB_CAP). */
+rk_status rk_scratch_size(rk_ctx *ctx, const rk_plan *plan, uint64_t n, uint64_t *bytes);
+
+/* Count pass: scans text_dev[0..n) once, stages hits in scratch_dev and writes
+ * the number of hits over all patterns to *total_host.  Synchronises s.
+ * scratch must hold rk_scratch_size bytes (RK_ENOSPACE otherwise) and must be
+ * passed unchanged to the rk_collect that follows. */
+rk_status rk_count(rk_ctx *ctx, const rk_plan *plan, const uint8_t *text_dev, uint64_t n,
+                   void *scratch_dev, uint64_t scratch_bytes, uint64_t *total_host, rk_stream s);
+
+/* Bytes of device work memory rk_collect needs when the count was `total`
+ * (0 for single-pattern plans). */
+rk_status rk_work_size(rk_ctx *ctx, const rk_plan *plan, uint64_t total, uint64_t *bytes);
+
+/* Collect pass, after rk_count with the same plan, text and scratch: writes
+ * offsets_dev[0..k] (offsets_dev[j+1] - offsets_dev[j] = hits of pattern j,
+ * offsets_dev[0] = 0) and positions_dev[offsets[j] .. offsets[j+1]) = pattern
+ * j's positions, strictly ascending.  capacity = entries of positions_dev
+ * (RK_ENOSPACE if below the total).  Does not synchronise s. */
+rk_status rk_collect(rk_ctx *ctx, const rk_plan *plan, const uint8_t *text_dev, uint64_t n,
+                     void *scratch_dev, uint64_t scratch_bytes, void *work_dev, uint64_t work_bytes,
+                     uint64_t *offsets_dev, uint64_t *positions_dev, uint64_t capacity, rk_stream s);
+
+/* Window hashes: out_dev[i] = hash(text_dev[xs_dev[i] .. xs_dev[i]+m)) in [0, q),
+ * each evaluated directly (Horner) on the device.  Every xs_dev[i] must satisfy
+ * xs + m <= n; out-of-range entries get the value UINT64_MAX. */
+rk_status rk_window_hashes(rk_ctx *ctx, const uint8_t *text_dev, uint64_t n, uint32_t m,
+                           const uint64_t *xs_dev, uint64_t cnt, uint64_t *out_dev, rk_stream s);
+
+/* Hash dump of the scan itself: runs the exact-mode scan kernel for length m
+ * over text_dev[0..n) and writes, from its rolling state, the hash of window
+ * x = i * stride to out_dev[i] for i < cnt = floor((n - m) / stride) + 1.
+ * cap = entries of out_dev (RK_ENOSPACE if below cnt). */
+rk_status rk_scan_dump(rk_ctx *ctx, const uint8_t *text_dev, uint64_t n, uint32_t m,
+                       uint64_t stride, uint64_t *out_dev, uint64_t cap, rk_stream s);
+
+/* ----------------------------------------------------------------- batching */
+
+/* One search instance of a batch: text on the device (16-byte aligned), its
+ * patterns on the host (same layout as rk_plan_create). */
+typedef struct {
+  const uint8_t *text_dev;
+  uint64_t n;
+  const uint8_t *bytes_host;
+  const uint64_t *offsets_host;
+  uint32_t k;
+} rk_instance;
+
+/* Plan for `count` independent searches scanned by one persistent launch over
+ * a work queue of tiles ordered by pattern-length bucket.  Instance i's
+ * patterns get global ids base_i + j with base_i = sum of k over instances
+ * before i.  The plan keeps the text pointers; the texts must stay alive and
+ * unchanged while the plan is used. */
+rk_status rk_batch_plan_create(rk_ctx *ctx, const rk_instance *inst, uint32_t count, int mode,
+                               rk_plan **out);
+/* rk_count / rk_collect on a batch plan: text_dev must be NULL and n is the
+ * total text bytes over instances (as passed to rk_scratch_size); offsets_dev
+ * has (sum k) + 1 entries; positions are relative to each instance's text. */
+uint64_t rk_plan_text_bytes(const rk_plan *plan);
+
+/* ---------------------------------------------------------------- autotuner */
+
+/* Times every scan geometry of the built-in table on a synthetic text of n
+ * bytes for pattern length m (both modes), verifies each candidate's hits
+ * against the first, and stores the fastest per (mode, length class) in the
+ * context.  If path is non-NULL the table is also written there as JSON.
+ * Synchronises the device. */
+rk_status rk_autotune(rk_ctx *ctx, uint64_t n, const uint32_t *lengths, uint32_t nlengths,
+                      const char *path);
+/* Load a table written by rk_autotune (entries for another gfx arch are ignored). */
+rk_status rk_autotune_load(rk_ctx *ctx, const char *path);
+/* Geometry index the scan uses for (mode, pattern length m). */
+int rk_autotune_choice(const rk_ctx *ctx, int mode, uint32_t m);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RK_H */

@@ -1,0 +1,516 @@
+// Plan construction, scratch layout and the launch sequences of the count and
+// collect passes (single search and batch), plus the hash dump.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <new>
+#include <vector>
+
+#include "../../include/rk.h"
+#include "rk_internal.h"
+#include "rk_runtime.h"
+
+namespace rk {
+
+// images are built per real instance (defined in rk_host.cpp)
+struct BucketIn;
+rk_status build_instance_images(rk_ctx *ctx, const uint8_t *bytes, const uint64_t *offs, uint32_t k,
+                                uint32_t pid_base, int mode, uint32_t src, std::vector<VInst> &vinsts,
+                                std::vector<uint8_t> &blob);
+
+static inline uint64_t align_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
+
+static int pick_cfg(const rk_ctx *ctx, int mode, uint32_t m) {
+  if (ctx->tile_cfg >= 0) return ctx->tile_cfg;
+  const int md = mode == RK_MODE_EXACT ? 1 : 2;
+  if (m >= 1 && m <= RK_MAX_M && ctx->tune[md][m] >= 0) return ctx->tune[md][m];
+  return 0;
+}
+
+rk_status plan_build(rk_ctx *ctx, const rk_instance *inst, uint32_t count, int mode, bool batch, rk_plan **out) {
+  if (mode == RK_MODE_AUTO) mode = RK_MODE_SCREEN;
+  if (mode != RK_MODE_EXACT && mode != RK_MODE_SCREEN) return set_err(ctx, RK_EINVAL, "unknown mode %d", mode);
+  if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, RK_EDEVICE, "hipSetDevice failed");
+  rk_plan *P = new (std::nothrow) rk_plan();
+  if (!P) return set_err(ctx, RK_ENOMEM, "plan allocation");
+  P->device = ctx->device;
+  P->mode = mode;
+  P->batch = batch;
+  std::vector<uint8_t> blob;
+  uint64_t ktot = 0;
+  // weight of each length (bytes x patterns) to pick one scan geometry
+  std::map<uint32_t, double> mweight;
+  for (uint32_t i = 0; i < count; ++i) {
+    const rk_instance &I = inst[i];
+    if (batch) {
+      if (I.n && !I.text_dev) {
+        delete P;
+        return set_err(ctx, RK_EINVAL, "instance %u: null text", i);
+      }
+      if (((uintptr_t)I.text_dev & 15u) != 0) {
+        delete P;
+        return set_err(ctx, RK_EINVAL, "instance %u: text not 16-byte aligned", i);
+      }
+      if (I.n > RK_MAX_N) {
+        delete P;
+        return set_err(ctx, RK_EUNSUPPORTED, "instance %u: text too long", i);
+      }
+    }
+    if (ktot + I.k > RK_MAX_PID) {
+      delete P;
+      return set_err(ctx, RK_EUNSUPPORTED, "more than %u patterns in one plan", RK_MAX_PID);
+    }
+    RealInst R;
+    R.text = I.text_dev;
+    R.n = I.n;
+    R.pid_base = (uint32_t)ktot;
+    R.k = I.k;
+    P->insts.push_back(R);
+    rk_status st = build_instance_images(ctx, I.bytes_host, I.offsets_host, I.k, (uint32_t)ktot, mode, i,
+                                         P->vinsts, blob);
+    if (st != RK_OK) {
+      delete P;
+      return st;
+    }
+    for (uint32_t j = 0; j < I.k; ++j) {
+      const uint32_t m = (uint32_t)(I.offsets_host[j + 1] - I.offsets_host[j]);
+      mweight[m] += (double)(batch ? I.n : 1) + 1.0;
+    }
+    ktot += I.k;
+    P->text_bytes += batch ? I.n : 0;
+  }
+  P->k_total = (uint32_t)ktot;
+  uint32_t best_m = 8;
+  double bw = -1;
+  for (auto &kv : mweight)
+    if (kv.second > bw) {
+      bw = kv.second;
+      best_m = kv.first;
+    }
+  P->cfg = pick_cfg(ctx, mode, best_m);
+  P->fam = mode == RK_MODE_EXACT ? kFamExact : kFamScreen1;
+  for (const VInst &v : P->vinsts)
+    if (mode != RK_MODE_EXACT && !v.only_one_list) P->fam = kFamScreen;
+  for (const VInst &v : P->vinsts) P->img_cap = std::max(P->img_cap, v.img_bytes);
+  P->img_cap = (uint32_t)align_up(P->img_cap, 16);
+
+  // batch: fixed instance descriptors and the work-queue order
+  std::vector<InstDesc> descs;
+  std::vector<uint64_t> items;
+  if (batch) {
+    const uint32_t W = kTileCfgs[P->cfg].wg * kTileCfgs[P->cfg].c;
+    uint64_t base = 0;
+    for (const VInst &v : P->vinsts) {
+      const RealInst &R = P->insts[v.src];
+      InstDesc d;
+      memset(&d, 0, sizeof d);
+      d.text = R.text;
+      d.n = R.n;
+      d.tile_base = base;
+      d.ntiles = (R.n + W - 1) / W;
+      d.img_off = v.img_off;
+      d.img_bytes = v.img_bytes;
+      descs.push_back(d);
+      base += d.ntiles;
+    }
+    P->total_tiles = base;
+    // queue order: heavier tiles (more buckets, longer patterns) first, then by
+    // instance, so a workgroup keeps one instance image across consecutive pops
+    std::vector<uint32_t> order(P->vinsts.size());
+    for (uint32_t i = 0; i < order.size(); ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
+      const VInst &x = P->vinsts[a], &y = P->vinsts[b];
+      if (x.nbuckets != y.nbuckets) return x.nbuckets > y.nbuckets;
+      return x.max_m > y.max_m;
+    });
+    for (uint32_t vi : order)
+      for (uint64_t t = 0; t < descs[vi].ntiles; ++t) items.push_back(descs[vi].tile_base + t);
+    P->nitems = items.size();
+  }
+  const uint64_t blob_bytes = align_up(std::max<size_t>(blob.size(), 16), 256);
+  const uint64_t desc_bytes = align_up(descs.size() * sizeof(InstDesc), 256);
+  const uint64_t item_bytes = align_up(items.size() * 8, 256);
+  const uint64_t all = blob_bytes + desc_bytes + item_bytes;
+  if (hipMalloc(&P->dev, all) != hipSuccess) {
+    delete P;
+    return set_err(ctx, RK_ENOMEM, "plan device memory (%llu bytes)", (unsigned long long)all);
+  }
+  P->blob_dev = (uint8_t *)P->dev;
+  P->inst_dev = descs.empty() ? nullptr : (InstDesc *)((uint8_t *)P->dev + blob_bytes);
+  P->items_dev = items.empty() ? nullptr : (uint64_t *)((uint8_t *)P->dev + blob_bytes + desc_bytes);
+  hipError_t e = hipSuccess;
+  if (!blob.empty()) e = hipMemcpy(P->blob_dev, blob.data(), blob.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !descs.empty())
+    e = hipMemcpy(P->inst_dev, descs.data(), descs.size() * sizeof(InstDesc), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !items.empty())
+    e = hipMemcpy(P->items_dev, items.data(), items.size() * 8, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    rk_status st = hip_err(ctx, e, "plan upload");
+    hipFree(P->dev);
+    delete P;
+    return st;
+  }
+  *out = P;
+  return RK_OK;
+}
+
+rk_status make_layout(rk_ctx *ctx, const rk_plan *plan, uint64_t n, Layout &L) {
+  L = Layout();
+  L.W = kTileCfgs[plan->cfg].wg * kTileCfgs[plan->cfg].c;
+  if (plan->batch) {
+    L.T = plan->total_tiles;
+  } else {
+    if (n > RK_MAX_N) return set_err(ctx, RK_EUNSUPPORTED, "text longer than 2^40-1 bytes");
+    L.T1 = (n + L.W - 1) / L.W;
+    L.T = L.T1 * plan->vinsts.size();
+  }
+  L.S = ctx->slab_cap ? ctx->slab_cap : L.W / 64;
+  uint64_t o = 0;
+  auto take = [&o](uint64_t bytes) {
+    const uint64_t r = o;
+    o = align_up(o + bytes, 256);
+    return r;
+  };
+  L.ctr = take(256);
+  L.inst = take(plan->batch ? 0 : plan->vinsts.size() * sizeof(InstDesc));
+  L.counts = take(L.T * 4);
+  L.offsets = take(L.T * 8);
+  L.ovf = take(L.T * 8);
+  L.tmp = take(scan_tmp_words(L.T) * 8);
+  L.slabs = take(L.T * (uint64_t)L.S * 8);
+  L.total = o;
+  return RK_OK;
+}
+
+struct WorkLayout {
+  uint64_t nblk = 0, a = 0, b = 0, ghist = 0, goff = 0, tmp = 0, total = 0;
+};
+
+static WorkLayout work_layout(uint64_t total) {
+  WorkLayout w;
+  w.nblk = radix_blocks(total);
+  uint64_t o = 0;
+  auto take = [&o](uint64_t bytes) {
+    const uint64_t r = o;
+    o = align_up(o + bytes, 256);
+    return r;
+  };
+  w.a = take(total * 8);
+  w.b = take(total * 8);
+  w.ghist = take(256 * w.nblk * 4);
+  w.goff = take(256 * w.nblk * 8);
+  w.tmp = take(scan_tmp_words(256 * w.nblk) * 8);
+  w.total = o;
+  return w;
+}
+
+uint64_t work_bytes_for(const rk_plan *plan, uint64_t total) {
+  if (plan->k_total <= 1) return 0;
+  return work_layout(total).total;
+}
+
+static uint32_t npasses(uint32_t k) {
+  uint32_t p = 0;
+  uint64_t cap = 1;
+  while (cap < k) {
+    cap <<= 8;
+    ++p;
+  }
+  return p;
+}
+
+static hipError_t prof_begin(rk_ctx *ctx, hipStream_t s, int kind, int *slot) {
+  *slot = -1;
+  if (!ctx->profile) return hipSuccess;
+  ProfEvent ev;
+  if (!ctx->free_events.empty()) {
+    ev = ctx->free_events.back();
+    ctx->free_events.pop_back();
+  } else {
+    hipError_t e = hipEventCreate(&ev.a);
+    if (e != hipSuccess) return e;
+    e = hipEventCreate(&ev.b);
+    if (e != hipSuccess) return e;
+  }
+  ev.kind = kind;
+  ctx->prof_events.push_back(ev);
+  *slot = (int)ctx->prof_events.size() - 1;
+  return hipEventRecord(ev.a, s);
+}
+
+static hipError_t prof_end(rk_ctx *ctx, hipStream_t s, int slot) {
+  if (slot < 0) return hipSuccess;
+  return hipEventRecord(ctx->prof_events[slot].b, s);
+}
+
+static uint32_t scan_grid(rk_ctx *ctx, int cfg, int fam, uint32_t lds, uint64_t nitems) {
+  if (ctx->grid) return (uint32_t)std::min<uint64_t>(ctx->grid, std::max<uint64_t>(nitems, 1));
+  int blocks = 0;
+  if (scan_occupancy(cfg, fam, lds, &blocks) != hipSuccess || blocks < 1) blocks = 1;
+  const uint64_t g = (uint64_t)ctx->num_cu * (uint64_t)blocks;
+  return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(g, nitems));
+}
+
+// Fills ScanParams common to the count pass and the rescan.
+static void base_params(const rk_plan *plan, const Layout &L, uint8_t *sc, ScanParams &p) {
+  memset(&p, 0, sizeof p);
+  if (plan->batch) {
+    p.inst = plan->inst_dev;
+    p.ninst = (uint32_t)plan->vinsts.size();
+  } else {
+    p.inst = (const InstDesc *)(sc + L.inst);
+    p.ninst = (uint32_t)plan->vinsts.size();
+  }
+  p.img_cap = plan->img_cap;
+  p.blob = plan->blob_dev;
+  p.tile_counts = (uint32_t *)(sc + L.counts);
+  p.slab_cap = L.S;
+  p.total = (unsigned long long *)(sc + L.ctr);
+  p.ovf_count = (uint32_t *)(sc + L.ctr + 8);
+  p.ovf_list = (uint64_t *)(sc + L.ovf);
+  p.grab = 1;
+}
+
+rk_status count_enqueue(rk_ctx *ctx, const rk_plan *plan, const uint8_t *text, uint64_t n, void *scratch,
+                        uint64_t scratch_bytes, hipStream_t s) {
+  if (plan->device != ctx->device) return set_err(ctx, RK_EINVAL, "plan belongs to another device");
+  if (plan->batch) {
+    if (text) return set_err(ctx, RK_EINVAL, "batch plans take text_dev = NULL");
+  } else {
+    if (n && !text) return set_err(ctx, RK_EINVAL, "null text");
+    if (((uintptr_t)text & 15u) != 0) return set_err(ctx, RK_EINVAL, "text_dev must be 16-byte aligned");
+  }
+  Layout L;
+  rk_status st = make_layout(ctx, plan, n, L);
+  if (st != RK_OK) return st;
+  if (scratch_bytes < L.total) return set_err(ctx, RK_ENOSPACE, "scratch needs %llu bytes, got %llu",
+                                              (unsigned long long)L.total, (unsigned long long)scratch_bytes);
+  if (!scratch) return set_err(ctx, RK_EINVAL, "null scratch");
+  if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, RK_EDEVICE, "hipSetDevice failed");
+  uint8_t *sc = (uint8_t *)scratch;
+  hipError_t e;
+  if (!plan->batch && !plan->vinsts.empty()) {
+    // instance descriptors of this text (one per virtual instance)
+    std::vector<InstDesc> d(plan->vinsts.size());
+    for (size_t i = 0; i < d.size(); ++i) {
+      memset(&d[i], 0, sizeof(InstDesc));
+      d[i].text = text;
+      d[i].n = n;
+      d[i].tile_base = L.T1 * i;
+      d[i].ntiles = L.T1;
+      d[i].img_off = plan->vinsts[i].img_off;
+      d[i].img_bytes = plan->vinsts[i].img_bytes;
+    }
+    const size_t bytes = d.size() * sizeof(InstDesc);
+    // hipMemcpyAsync from pageable memory stages the data before returning
+    e = hipMemcpyAsync(sc + L.inst, d.data(), bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_err(ctx, e, "instance upload");
+  }
+  e = launch_fill_u32((uint32_t *)(sc + L.ctr), 64, 0u, s);
+  if (e != hipSuccess) return hip_err(ctx, e, "counter reset");
+  if (L.T == 0) return RK_OK;
+  ScanParams p;
+  base_params(plan, L, sc, p);
+  p.items = plan->batch ? plan->items_dev : nullptr;
+  p.nitems = plan->batch ? plan->nitems : L.T;
+  p.out = (uint64_t *)(sc + L.slabs);
+  const bool use_queue = ctx->queue == 1 || (ctx->queue == -1 && plan->batch);
+  if (use_queue) {
+    p.queue = (uint32_t *)(sc + L.ctr + 12);
+    p.grab = 1;
+  }
+  const uint32_t lds = scan_lds_bytes(plan->cfg, plan->img_cap);
+  const uint32_t grid = scan_grid(ctx, plan->cfg, plan->fam, lds, p.nitems);
+  int slot;
+  e = prof_begin(ctx, s, 0, &slot);
+  if (e != hipSuccess) return hip_err(ctx, e, "profiling event");
+  e = launch_scan(plan->cfg, plan->fam, p, grid, lds, s);
+  if (e != hipSuccess) return hip_err(ctx, e, "scan launch");
+  e = prof_end(ctx, s, slot);
+  if (e != hipSuccess) return hip_err(ctx, e, "profiling event");
+  CountMemo &mm = ctx->memo[ctx->memo_next++ % 16];
+  mm.scratch = scratch;
+  mm.plan = plan;
+  mm.n = n;
+  mm.total = ~0ull;  // filled by count_finish
+  return RK_OK;
+}
+
+rk_status count_finish(rk_ctx *ctx, const rk_plan *plan, void *scratch, hipStream_t s, uint64_t *total) {
+  hipError_t e = hipMemcpyAsync(ctx->pinned, scratch, 16, hipMemcpyDeviceToHost, s);
+  if (e != hipSuccess) return hip_err(ctx, e, "total readback");
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_err(ctx, e, "scan");
+  *total = ctx->pinned[0];
+  for (auto &mm : ctx->memo)
+    if (mm.scratch == scratch && mm.plan == plan) mm.total = *total;
+  return RK_OK;
+}
+
+rk_status collect_enqueue(rk_ctx *ctx, const rk_plan *plan, const uint8_t *text, uint64_t n, void *scratch,
+                          uint64_t scratch_bytes, void *work, uint64_t work_bytes, uint64_t *offsets,
+                          uint64_t *positions, uint64_t capacity, hipStream_t s) {
+  (void)text;
+  if (!offsets) return set_err(ctx, RK_EINVAL, "null offsets");
+  Layout L;
+  rk_status st = make_layout(ctx, plan, n, L);
+  if (st != RK_OK) return st;
+  if (scratch_bytes < L.total || !scratch) return set_err(ctx, RK_ENOSPACE, "scratch too small");
+  if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, RK_EDEVICE, "hipSetDevice failed");
+  uint8_t *sc = (uint8_t *)scratch;
+  // total of the matching count pass
+  uint64_t total = ~0ull;
+  for (auto &mm : ctx->memo)
+    if (mm.scratch == scratch && mm.plan == plan && mm.n == n && mm.total != ~0ull) total = mm.total;
+  hipError_t e;
+  if (total == ~0ull) {
+    e = hipMemcpyAsync(ctx->pinned, sc + L.ctr, 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_err(ctx, e, "total readback");
+    total = ctx->pinned[0];
+  }
+  if (capacity < total) return set_err(ctx, RK_ENOSPACE, "positions capacity %llu < %llu hits",
+                                       (unsigned long long)capacity, (unsigned long long)total);
+  if (total && !positions) return set_err(ctx, RK_EINVAL, "null positions");
+  const uint32_t k = plan->k_total;
+  const uint64_t need = work_bytes_for(plan, total);
+  if (work_bytes < need || (need && !work))
+    return set_err(ctx, RK_ENOSPACE, "work needs %llu bytes, got %llu", (unsigned long long)need,
+                   (unsigned long long)work_bytes);
+  int slot;
+  e = prof_begin(ctx, s, 2, &slot);
+  if (e != hipSuccess) return hip_err(ctx, e, "profiling event");
+  if (k == 0) {
+    e = launch_fill_u32((uint32_t *)offsets, 2, 0u, s);
+    if (e != hipSuccess) return hip_err(ctx, e, "offsets");
+    return hip_err_or_ok(ctx, prof_end(ctx, s, slot));
+  }
+  if (total == 0) {
+    // every count is zero
+    e = launch_fill_u32((uint32_t *)offsets, 2ull * (k + 1), 0u, s);
+    if (e != hipSuccess) return hip_err(ctx, e, "offsets");
+    return hip_err_or_ok(ctx, prof_end(ctx, s, slot));
+  }
+  uint64_t *tile_off = (uint64_t *)(sc + L.offsets);
+  e = launch_exclusive_scan((const uint32_t *)(sc + L.counts), L.T, tile_off, (uint64_t *)(sc + L.tmp), nullptr, s);
+  if (e != hipSuccess) return hip_err(ctx, e, "tile scan");
+  WorkLayout WL = work_layout(total);
+  uint64_t *target = k == 1 ? positions : (uint64_t *)((uint8_t *)work + WL.a);
+  e = launch_compact((const uint32_t *)(sc + L.counts), tile_off, L.T, (const uint64_t *)(sc + L.slabs), L.S, target,
+                     s);
+  if (e != hipSuccess) return hip_err(ctx, e, "compact");
+  e = prof_end(ctx, s, slot);
+  if (e != hipSuccess) return hip_err(ctx, e, "profiling event");
+  // rescan of tiles whose hits did not fit their slab (count read on the device)
+  {
+    ScanParams p;
+    base_params(plan, L, sc, p);
+    p.items = (const uint64_t *)(sc + L.ovf);
+    p.nitems = L.T;
+    p.nitems_dev = (const uint32_t *)(sc + L.ctr + 8);
+    p.out = target;
+    p.tile_offsets = tile_off;
+    p.direct = 1;
+    const uint32_t lds = scan_lds_bytes(plan->cfg, plan->img_cap);
+    const uint32_t grid = std::min<uint32_t>(scan_grid(ctx, plan->cfg, plan->fam, lds, L.T), (uint32_t)ctx->num_cu);
+    e = prof_begin(ctx, s, 1, &slot);
+    if (e != hipSuccess) return hip_err(ctx, e, "profiling event");
+    e = launch_scan(plan->cfg, plan->fam, p, grid, lds, s);
+    if (e != hipSuccess) return hip_err(ctx, e, "rescan launch");
+    e = prof_end(ctx, s, slot);
+    if (e != hipSuccess) return hip_err(ctx, e, "profiling event");
+  }
+  e = prof_begin(ctx, s, 2, &slot);
+  if (e != hipSuccess) return hip_err(ctx, e, "profiling event");
+  if (k == 1) {
+    e = launch_single_offsets(offsets, total, s);
+    if (e != hipSuccess) return hip_err(ctx, e, "offsets");
+  } else {
+    uint8_t *wk = (uint8_t *)work;
+    uint64_t *res = nullptr;
+    e = launch_radix((uint64_t *)(wk + WL.a), (uint64_t *)(wk + WL.b), total, npasses(k), (uint32_t *)(wk + WL.ghist),
+                     (uint64_t *)(wk + WL.goff), (uint64_t *)(wk + WL.tmp), &res, s);
+    if (e != hipSuccess) return hip_err(ctx, e, "radix sort");
+    e = launch_pid_offsets(res, total, k, offsets, s);
+    if (e != hipSuccess) return hip_err(ctx, e, "offsets");
+    e = launch_strip(res, total, positions, s);
+    if (e != hipSuccess) return hip_err(ctx, e, "strip");
+  }
+  e = prof_end(ctx, s, slot);
+  if (e != hipSuccess) return hip_err(ctx, e, "profiling event");
+  return RK_OK;
+}
+
+}  // namespace rk
+
+using namespace rk;
+
+extern "C" rk_status rk_scan_dump(rk_ctx *ctx, const uint8_t *text, uint64_t n, uint32_t m, uint64_t stride,
+                                  uint64_t *out, uint64_t cap, rk_stream s) {
+  if (!ctx) return RK_EINVAL;
+  if (m == 0) return set_err(ctx, RK_EINVAL, "m = 0");
+  if (m > RK_MAX_M) return set_err(ctx, RK_EUNSUPPORTED, "m > %u", RK_MAX_M);
+  if (stride == 0) return set_err(ctx, RK_EINVAL, "stride = 0");
+  if (n < m) return RK_OK;
+  if (!text || !out) return set_err(ctx, RK_EINVAL, "null pointer");
+  if (((uintptr_t)text & 15u) != 0) return set_err(ctx, RK_EINVAL, "text_dev must be 16-byte aligned");
+  if (n > RK_MAX_N) return set_err(ctx, RK_EUNSUPPORTED, "text too long");
+  const uint64_t cnt = (n - m) / stride + 1;
+  if (cap < cnt) return set_err(ctx, RK_ENOSPACE, "dump needs %llu entries", (unsigned long long)cnt);
+  if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, RK_EDEVICE, "hipSetDevice failed");
+  hipStream_t st = (hipStream_t)s;
+  const int cfg = ctx->tile_cfg >= 0 ? ctx->tile_cfg : 0;
+  const uint32_t W = kTileCfgs[cfg].wg * kTileCfgs[cfg].c;
+  // image: header + one kDump bucket; then the instance descriptor
+  uint8_t host[256];
+  memset(host, 0, sizeof host);
+  ImageHeader hd = {1u, 128u, m, 0u};
+  BucketDesc d;
+  memset(&d, 0, sizeof d);
+  d.m = m;
+  d.kind = kDump;
+  d.mask = 0xFFFFFFFFu;
+  memcpy(host, &hd, sizeof hd);
+  memcpy(host + sizeof hd, &d, sizeof d);
+  InstDesc I;
+  memset(&I, 0, sizeof I);
+  I.text = text;
+  I.n = n;
+  I.tile_base = 0;
+  I.ntiles = (n + W - 1) / W;
+  I.img_off = 0;
+  I.img_bytes = 128;
+  memcpy(host + 128, &I, sizeof I);
+  hipError_t e;
+  if (!ctx->dump_dev) {
+    e = hipMalloc(&ctx->dump_dev, 256);
+    if (e != hipSuccess) return hip_err(ctx, e, "dump buffer");
+  }
+  e = hipMemcpyAsync(ctx->dump_dev, host, 256, hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return hip_err(ctx, e, "dump upload");
+  ScanParams p;
+  memset(&p, 0, sizeof p);
+  p.inst = (const InstDesc *)((uint8_t *)ctx->dump_dev + 128);
+  p.ninst = 1;
+  p.img_cap = 128;
+  p.blob = (const uint8_t *)ctx->dump_dev;
+  p.nitems = I.ntiles;
+  p.direct = 1;
+  p.dump_out = out;
+  p.dump_stride = stride;
+  p.dump_cap = cap;
+  const uint32_t lds = scan_lds_bytes(cfg, 128);
+  uint32_t grid = (uint32_t)std::min<uint64_t>(I.ntiles, (uint64_t)ctx->num_cu * 4);
+  e = launch_scan(cfg, kFamExact, p, grid, lds, st);
+  if (e != hipSuccess) return hip_err(ctx, e, "dump launch");
+  e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_err(ctx, e, "dump");
+  return RK_OK;
+}
+
+extern "C" rk_status rk_autotune(rk_ctx *ctx, uint64_t n, const uint32_t *lengths, uint32_t nlengths,
+                                 const char *path) {
+  return tune_run(ctx, n, lengths, nlengths, path);
+}

@@ -1,0 +1,541 @@
+// Host runtime of librk: contexts, pattern preprocessing (plans), scratch
+// layout, launch orchestration of the count and collect passes, profiling and
+// the scan-geometry autotuner.  Every entry point of include/rk.h except the
+// server lives here.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/rk.h"
+#include "rk_internal.h"
+#include "rk_runtime.h"
+
+namespace rk {
+
+// ------------------------------------------------------------ host arithmetic
+// The library's own mod 2^61-1 arithmetic for d = 256 (pattern hashes are
+// computed once on the host, Sec. 3.1).  256*s is a rotation of the 61-bit word.
+static inline uint64_t h_mul256(uint64_t s) { return ((s << 8) & kQ) + (s >> 53); }
+static inline uint64_t h_canon(uint64_t s) {
+  uint64_t f = (s & kQ) + (s >> 61);
+  return f >= kQ ? f - kQ : f;
+}
+uint64_t host_hash(const uint8_t *p, uint64_t m) {
+  uint64_t s = 0;
+  for (uint64_t i = 0; i < m; ++i) s = h_canon(h_mul256(s) + p[i]);
+  return s;
+}
+// screen shift for a pattern length: the smallest power of two s with s*m >= 32
+// and s >= 2 (s = 1 is the paper's shift-and-add form; s = 2 keeps the warm-up
+// at 15 bytes while every byte of a window of length >= 16 still contributes)
+uint32_t screen_shift(uint32_t m) {
+  if (m < 8) return 8;
+  if (m < 16) return 4;
+  return 2;
+}
+uint32_t screen_hash(const uint8_t *p, uint32_t m) {
+  const uint32_t s = screen_shift(m);
+  uint32_t h = 0;
+  for (uint32_t i = 0; i < m; ++i) h = (h << s) + p[i];
+  if (s == 8 && m < 4) h &= (1u << (8 * m)) - 1u;
+  return h;
+}
+
+// ------------------------------------------------------------------ errors
+rk_status set_err(rk_ctx *ctx, rk_status st, const char *fmt, ...) {
+  if (ctx) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    ctx->err = buf;
+  }
+  return st;
+}
+
+rk_status hip_err(rk_ctx *ctx, hipError_t e, const char *what) {
+  return set_err(ctx, RK_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(ctx, expr, what)                 \
+  do {                                           \
+    hipError_t e_ = (expr);                      \
+    if (e_ != hipSuccess) return hip_err(ctx, e_, what); \
+  } while (0)
+
+static inline uint64_t align_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
+static inline uint32_t next_pow2(uint32_t v) {
+  uint32_t p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+// ------------------------------------------------------------ image building
+struct BucketIn {
+  uint32_t m;
+  std::vector<uint32_t> pids;        // global pattern ids (ascending)
+  std::vector<const uint8_t *> pats; // pattern bytes
+};
+
+static bool build_fp_table(const std::vector<uint32_t> &keys, uint32_t bits, std::vector<uint32_t> &tab) {
+  const uint32_t S = 1u << bits;
+  tab.assign(S, 0);
+  std::vector<uint8_t> cnt(S, 0);
+  for (uint32_t h : keys) {
+    const uint32_t slot = h & (S - 1);
+    const uint32_t f = h >> 16;
+    if (cnt[slot] == 0) {
+      tab[slot] = f | (f << 16);
+      cnt[slot] = 1;
+    } else if (cnt[slot] == 1) {
+      if ((tab[slot] & 0xFFFFu) == f) continue;
+      tab[slot] = (tab[slot] & 0xFFFFu) | (f << 16);
+      cnt[slot] = 2;
+    } else {
+      if ((tab[slot] & 0xFFFFu) == f || (tab[slot] >> 16) == f) continue;
+      return false;
+    }
+  }
+  return true;
+}
+
+// Appends one bucket's tables to img (16-aligned) and fills its descriptor.
+// Returns false if the bucket's key set does not fit the fingerprint table
+// limit (the caller then splits the bucket).
+static bool emit_bucket(const BucketIn &B, int mode, std::vector<uint8_t> &img, BucketDesc &D) {
+  const uint32_t m = B.m, np = (uint32_t)B.pids.size();
+  memset(&D, 0, sizeof D);
+  D.m = m;
+  D.npat = np;
+  D.mask = 0xFFFFFFFFu;
+  std::vector<uint64_t> hx(np);
+  for (uint32_t i = 0; i < np; ++i) hx[i] = host_hash(B.pats[i], m);
+  // distinct exact hashes -> chains of local indices (ascending)
+  std::vector<uint64_t> dist;
+  std::vector<uint32_t> link(np, kNoLink);
+  std::map<uint64_t, uint32_t> head, tail;
+  for (uint32_t i = 0; i < np; ++i) {
+    auto it = head.find(hx[i]);
+    if (it == head.end()) {
+      head[hx[i]] = i;
+      tail[hx[i]] = i;
+      dist.push_back(hx[i]);
+    } else {
+      link[tail[hx[i]]] = i;
+      tail[hx[i]] = i;
+    }
+  }
+  std::vector<uint32_t> fpkeys;
+  std::vector<uint32_t> fptab;
+  if (mode == RK_MODE_EXACT) {
+    std::vector<uint32_t> lazy;
+    for (uint64_t H : dist) {
+      lazy.push_back((uint32_t)H);
+      lazy.push_back((uint32_t)(H + kQ));
+      if (H + 2 * kQ < (1ull << 62) + (1ull << 11)) lazy.push_back((uint32_t)(H + 2 * kQ));
+    }
+    if (lazy.size() <= 4) {
+      D.kind = kListExact;
+      for (int j = 0; j < 4; ++j) D.tgt[j] = lazy[j < (int)lazy.size() ? j : 0];
+    } else {
+      D.kind = kTableExact;
+      for (uint64_t H : dist) fpkeys.push_back((uint32_t)H);
+    }
+  } else {
+    D.shift = screen_shift(m);
+    if (D.shift == 8 && m < 4) D.mask = (1u << (8 * m)) - 1u;
+    std::vector<uint32_t> sh;
+    for (uint32_t i = 0; i < np; ++i) sh.push_back(screen_hash(B.pats[i], m));
+    std::sort(sh.begin(), sh.end());
+    sh.erase(std::unique(sh.begin(), sh.end()), sh.end());
+    if (sh.size() <= 4) {
+      D.kind = kListScreen;
+      for (int j = 0; j < 4; ++j) D.tgt[j] = sh[j < (int)sh.size() ? j : 0];
+      D.shift |= (sh.size() == 1 ? 1u : 4u) << 8;  // compare count the kernel unrolls
+    } else {
+      D.kind = kTableScreen;
+      fpkeys = sh;
+    }
+  }
+  auto put = [&img](const void *p, size_t bytes) -> uint32_t {
+    const uint32_t off = (uint32_t)align_up(img.size(), 16);
+    img.resize(off + align_up(bytes, 16), 0);
+    memcpy(img.data() + off, p, bytes);
+    return off;
+  };
+  if (D.kind == kTableScreen || D.kind == kTableExact) {
+    uint32_t bits = 6;
+    while ((1u << bits) < 2 * fpkeys.size()) ++bits;
+    bool ok = false;
+    for (; bits <= 13; ++bits)
+      if ((ok = build_fp_table(fpkeys, bits, fptab))) break;
+    if (!ok) return false;
+    D.fp_mask = (1u << bits) - 1;
+    D.fp_off = put(fptab.data(), fptab.size() * 4);
+  }
+  // exact open-addressing table
+  const uint32_t ES = std::max<uint32_t>(2, next_pow2(2 * (uint32_t)dist.size()));
+  std::vector<uint64_t> keys(ES, kEmptyKey);
+  std::vector<uint32_t> heads(ES, kNoLink);
+  for (uint64_t H : dist) {
+    uint32_t s = (uint32_t)H & (ES - 1);
+    while (keys[s] != kEmptyKey) s = (s + 1) & (ES - 1);
+    keys[s] = H;
+    heads[s] = head[H];
+  }
+  std::vector<uint8_t> ex(ES * 12);
+  memcpy(ex.data(), keys.data(), ES * 8);
+  memcpy(ex.data() + ES * 8, heads.data(), ES * 4);
+  D.ex_mask = ES - 1;
+  D.ex_off = put(ex.data(), ex.size());
+  D.link_off = put(link.data(), np * 4);
+  D.pid_off = put(B.pids.data(), np * 4);
+  std::vector<uint8_t> pb((size_t)np * m);
+  for (uint32_t i = 0; i < np; ++i) memcpy(pb.data() + (size_t)i * m, B.pats[i], m);
+  D.pat_off = put(pb.data(), pb.size());
+  return true;
+}
+
+// Splits buckets whose key sets do not fit one fingerprint table.
+static void expand_buckets(const BucketIn &B, int mode, std::vector<std::pair<BucketIn, std::vector<uint8_t>>> &out,
+                           std::vector<BucketDesc> &descs) {
+  std::vector<uint8_t> tmp;
+  BucketDesc D;
+  if (emit_bucket(B, mode, tmp, D) || B.pids.size() < 2) {
+    out.push_back({B, tmp});
+    descs.push_back(D);
+    return;
+  }
+  BucketIn a, b;
+  a.m = b.m = B.m;
+  const size_t h = B.pids.size() / 2;
+  a.pids.assign(B.pids.begin(), B.pids.begin() + h);
+  a.pats.assign(B.pats.begin(), B.pats.begin() + h);
+  b.pids.assign(B.pids.begin() + h, B.pids.end());
+  b.pats.assign(B.pats.begin() + h, B.pats.end());
+  expand_buckets(a, mode, out, descs);
+  expand_buckets(b, mode, out, descs);
+}
+
+// Builds the images of one real instance: buckets are packed greedily into
+// virtual instances whose image fits kImgLimit bytes.
+static rk_status build_images(rk_ctx *ctx, const std::vector<BucketIn> &buckets, int mode, uint32_t src_inst,
+                              std::vector<VInst> &vinsts, std::vector<uint8_t> &blob) {
+  std::vector<std::pair<BucketIn, std::vector<uint8_t>>> parts;
+  std::vector<BucketDesc> descs;
+  for (const BucketIn &B : buckets) expand_buckets(B, mode, parts, descs);
+  // a bucket with no table-fitting split (single pattern) always fits
+  size_t i = 0;
+  while (i < parts.size()) {
+    std::vector<uint8_t> img(sizeof(ImageHeader), 0);
+    std::vector<BucketDesc> ds;
+    std::vector<std::vector<uint8_t> *> bodies;
+    size_t j = i;
+    uint64_t body = 0;
+    uint32_t max_m = 0;
+    while (j < parts.size()) {
+      const uint64_t add = 64 + align_up(parts[j].second.size(), 16);
+      const uint64_t hdr = sizeof(ImageHeader) + 64 * (ds.size() + 1);
+      if (j > i && hdr + body + add > kImgLimit) break;
+      body += align_up(parts[j].second.size(), 16);
+      ds.push_back(descs[j]);
+      max_m = std::max(max_m, descs[j].m);
+      ++j;
+    }
+    const uint32_t hdr = (uint32_t)(sizeof(ImageHeader) + 64 * ds.size());
+    if (hdr + body > kImgLimit)
+      return set_err(ctx, RK_EUNSUPPORTED, "pattern bucket (m=%u) needs %llu bytes of LDS image (limit %u)",
+                     descs[i].m, (unsigned long long)(hdr + body), kImgLimit);
+    img.resize(hdr, 0);
+    for (size_t b = 0; b < ds.size(); ++b) {
+      const uint32_t base = (uint32_t)img.size();
+      const std::vector<uint8_t> &bb = parts[i + b].second;
+      img.insert(img.end(), bb.begin(), bb.end());
+      img.resize(align_up(img.size(), 16), 0);
+      BucketDesc d = ds[b];
+      if (d.kind == kTableScreen || d.kind == kTableExact) d.fp_off += base;
+      d.ex_off += base;
+      d.link_off += base;
+      d.pid_off += base;
+      d.pat_off += base;
+      memcpy(img.data() + sizeof(ImageHeader) + 64 * b, &d, 64);
+    }
+    ImageHeader hd;
+    hd.nbuckets = (uint32_t)ds.size();
+    hd.bytes = (uint32_t)align_up(img.size(), 16);
+    hd.max_m = max_m;
+    hd.pad = 0;
+    img.resize(hd.bytes, 0);
+    memcpy(img.data(), &hd, sizeof hd);
+    VInst v;
+    v.src = src_inst;
+    v.nbuckets = hd.nbuckets;
+    v.max_m = max_m;
+    for (const BucketDesc &d : ds)
+      if (d.kind != kListScreen || (d.shift >> 8) != 1u) v.only_one_list = false;
+    v.img_off = (uint32_t)align_up(blob.size(), 256);
+    v.img_bytes = hd.bytes;
+    blob.resize(v.img_off, 0);
+    blob.insert(blob.end(), img.begin(), img.end());
+    vinsts.push_back(v);
+    i = j;
+  }
+  return RK_OK;
+}
+
+static rk_status validate_patterns(rk_ctx *ctx, const uint8_t *bytes, const uint64_t *offs, uint32_t k) {
+  if (k > 0 && (!offs || (!bytes && offs[k] > offs[0])))
+    return set_err(ctx, RK_EINVAL, "null pattern arrays");
+  if (k > RK_MAX_PID) return set_err(ctx, RK_EUNSUPPORTED, "too many patterns (%u)", k);
+  for (uint32_t j = 0; j < k; ++j) {
+    if (offs[j + 1] <= offs[j]) return set_err(ctx, RK_EINVAL, "pattern %u has length 0", j);
+    if (offs[j + 1] - offs[j] > RK_MAX_M)
+      return set_err(ctx, RK_EUNSUPPORTED, "pattern %u has length %llu > %u", j,
+                     (unsigned long long)(offs[j + 1] - offs[j]), RK_MAX_M);
+  }
+  return RK_OK;
+}
+
+// Buckets (by length) of one instance's patterns with global ids from pid_base.
+static std::vector<BucketIn> bucketize(const uint8_t *bytes, const uint64_t *offs, uint32_t k, uint32_t pid_base) {
+  std::map<uint32_t, BucketIn> by_m;
+  for (uint32_t j = 0; j < k; ++j) {
+    const uint32_t m = (uint32_t)(offs[j + 1] - offs[j]);
+    BucketIn &B = by_m[m];
+    B.m = m;
+    B.pids.push_back(pid_base + j);
+    B.pats.push_back(bytes + offs[j]);
+  }
+  std::vector<BucketIn> out;
+  for (auto &kv : by_m) out.push_back(kv.second);
+  return out;
+}
+
+rk_status build_instance_images(rk_ctx *ctx, const uint8_t *bytes, const uint64_t *offs, uint32_t k,
+                                uint32_t pid_base, int mode, uint32_t src, std::vector<VInst> &vinsts,
+                                std::vector<uint8_t> &blob) {
+  rk_status st = validate_patterns(ctx, bytes, offs, k);
+  if (st != RK_OK) return st;
+  if (k == 0) return RK_OK;  // nothing to scan for
+  return build_images(ctx, bucketize(bytes, offs, k, pid_base), mode, src, vinsts, blob);
+}
+
+}  // namespace rk
+
+using namespace rk;
+
+// ===================================================================== C ABI
+extern "C" {
+
+const char *rk_status_string(rk_status s) {
+  switch (s) {
+    case RK_OK: return "RK_OK";
+    case RK_EINVAL: return "RK_EINVAL";
+    case RK_ENOMEM: return "RK_ENOMEM";
+    case RK_EUNSUPPORTED: return "RK_EUNSUPPORTED";
+    case RK_EDEVICE: return "RK_EDEVICE";
+    case RK_ENOSPACE: return "RK_ENOSPACE";
+    case RK_EBUSY: return "RK_EBUSY";
+    case RK_ECANCELED: return "RK_ECANCELED";
+  }
+  return "RK_UNKNOWN";
+}
+
+rk_status rk_ctx_create(int device, uint64_t d, uint64_t q, rk_ctx **out) {
+  if (!out) return RK_EINVAL;
+  *out = nullptr;
+  if (q != kQ || d != 256) return RK_EUNSUPPORTED;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return RK_EDEVICE;
+  if (hipSetDevice(device) != hipSuccess) return RK_EDEVICE;
+  rk_ctx *c = new (std::nothrow) rk_ctx();
+  if (!c) return RK_ENOMEM;
+  c->device = device;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+    delete c;
+    return RK_EDEVICE;
+  }
+  c->num_cu = prop.multiProcessorCount;
+  c->arch = prop.gcnArchName;
+  if (hipHostMalloc((void **)&c->pinned, 4096, hipHostMallocDefault) != hipSuccess) {
+    delete c;
+    return RK_ENOMEM;
+  }
+  for (int md = 0; md < 3; ++md)
+    for (int m = 0; m <= RK_MAX_M; ++m) c->tune[md][m] = -1;
+  *out = c;
+  return RK_OK;
+}
+
+void rk_ctx_destroy(rk_ctx *ctx) {
+  if (!ctx) return;
+  hipSetDevice(ctx->device);
+  for (auto &ev : ctx->prof_events) {
+    hipEventDestroy(ev.a);
+    hipEventDestroy(ev.b);
+  }
+  if (ctx->pinned) hipHostFree(ctx->pinned);
+  delete ctx;
+}
+
+const char *rk_ctx_last_error(const rk_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+rk_status rk_ctx_set_option(rk_ctx *ctx, int option, int64_t value) {
+  if (!ctx) return RK_EINVAL;
+  switch (option) {
+    case RK_OPT_SLAB_CAP:
+      if (value < 0 || value > (1 << 20)) return set_err(ctx, RK_EINVAL, "slab cap out of range");
+      ctx->slab_cap = (uint32_t)value;
+      return RK_OK;
+    case RK_OPT_TILE_CFG:
+      if (value < -1 || value >= kNumTileCfg) return set_err(ctx, RK_EINVAL, "tile cfg out of range");
+      ctx->tile_cfg = (int)value;
+      return RK_OK;
+    case RK_OPT_GRID:
+      if (value < 0 || value > (1 << 20)) return set_err(ctx, RK_EINVAL, "grid out of range");
+      ctx->grid = (uint32_t)value;
+      return RK_OK;
+    case RK_OPT_PROFILE:
+      ctx->profile = value != 0;
+      return RK_OK;
+    case RK_OPT_QUEUE:
+      if (value < -1 || value > 1) return set_err(ctx, RK_EINVAL, "queue option is -1, 0 or 1");
+      ctx->queue = (int)value;
+      return RK_OK;
+  }
+  return set_err(ctx, RK_EINVAL, "unknown option %d", option);
+}
+
+int rk_tile_cfg_count(void) { return kNumTileCfg; }
+
+rk_status rk_tile_cfg(int i, uint32_t *wg, uint32_t *c, uint32_t *tile) {
+  if (i < 0 || i >= kNumTileCfg) return RK_EINVAL;
+  if (wg) *wg = kTileCfgs[i].wg;
+  if (c) *c = kTileCfgs[i].c;
+  if (tile) *tile = kTileCfgs[i].wg * kTileCfgs[i].c;
+  return RK_OK;
+}
+
+rk_status rk_hash(const rk_ctx *ctx, const uint8_t *s, uint64_t m, uint64_t *out) {
+  (void)ctx;
+  if (!out || (m && !s)) return RK_EINVAL;
+  *out = host_hash(s, m);
+  return RK_OK;
+}
+
+rk_status rk_plan_create(rk_ctx *ctx, const uint8_t *bytes, const uint64_t *offs, uint32_t k, int mode,
+                         rk_plan **out) {
+  if (!ctx || !out) return RK_EINVAL;
+  *out = nullptr;
+  rk_instance inst;
+  inst.text_dev = nullptr;
+  inst.n = 0;
+  inst.bytes_host = bytes;
+  inst.offsets_host = offs;
+  inst.k = k;
+  return plan_build(ctx, &inst, 1, mode, false, out);
+}
+
+rk_status rk_batch_plan_create(rk_ctx *ctx, const rk_instance *inst, uint32_t count, int mode, rk_plan **out) {
+  if (!ctx || !out || (count && !inst)) return RK_EINVAL;
+  *out = nullptr;
+  return plan_build(ctx, inst, count, mode, true, out);
+}
+
+void rk_plan_destroy(rk_plan *plan) {
+  if (!plan) return;
+  hipSetDevice(plan->device);
+  if (plan->dev) hipFree(plan->dev);
+  delete plan;
+}
+
+uint32_t rk_plan_patterns(const rk_plan *plan) { return plan ? plan->k_total : 0; }
+uint64_t rk_plan_text_bytes(const rk_plan *plan) { return plan ? plan->text_bytes : 0; }
+
+rk_status rk_scratch_size(rk_ctx *ctx, const rk_plan *plan, uint64_t n, uint64_t *bytes) {
+  if (!ctx || !plan || !bytes) return RK_EINVAL;
+  Layout L;
+  rk_status st = make_layout(ctx, plan, n, L);
+  if (st != RK_OK) return st;
+  *bytes = L.total;
+  return RK_OK;
+}
+
+rk_status rk_work_size(rk_ctx *ctx, const rk_plan *plan, uint64_t total, uint64_t *bytes) {
+  if (!ctx || !plan || !bytes) return RK_EINVAL;
+  *bytes = work_bytes_for(plan, total);
+  return RK_OK;
+}
+
+rk_status rk_count(rk_ctx *ctx, const rk_plan *plan, const uint8_t *text, uint64_t n, void *scratch,
+                   uint64_t scratch_bytes, uint64_t *total_host, rk_stream s) {
+  if (!ctx || !plan || !total_host) return RK_EINVAL;
+  hipStream_t st = (hipStream_t)s;
+  uint64_t total = 0;
+  rk_status r = count_enqueue(ctx, plan, text, n, scratch, scratch_bytes, st);
+  if (r != RK_OK) return r;
+  r = count_finish(ctx, plan, scratch, st, &total);
+  if (r != RK_OK) return r;
+  *total_host = total;
+  return RK_OK;
+}
+
+rk_status rk_collect(rk_ctx *ctx, const rk_plan *plan, const uint8_t *text, uint64_t n, void *scratch,
+                     uint64_t scratch_bytes, void *work, uint64_t work_bytes, uint64_t *offsets,
+                     uint64_t *positions, uint64_t capacity, rk_stream s) {
+  if (!ctx || !plan) return RK_EINVAL;
+  return collect_enqueue(ctx, plan, text, n, scratch, scratch_bytes, work, work_bytes, offsets, positions,
+                         capacity, (hipStream_t)s);
+}
+
+rk_status rk_window_hashes(rk_ctx *ctx, const uint8_t *text, uint64_t n, uint32_t m, const uint64_t *xs,
+                           uint64_t cnt, uint64_t *out, rk_stream s) {
+  if (!ctx) return RK_EINVAL;
+  if (cnt == 0) return RK_OK;
+  if (!text || !xs || !out) return set_err(ctx, RK_EINVAL, "null pointer");
+  if (m == 0) return set_err(ctx, RK_EINVAL, "m = 0");
+  HIP_TRY(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+  HIP_TRY(ctx, launch_window_hashes(text, n, m, xs, cnt, out, (hipStream_t)s), "window_hashes launch");
+  return RK_OK;
+}
+
+rk_status rk_ctx_profile(rk_ctx *ctx, int kernel, uint64_t *launches, double *total_ms) {
+  if (!ctx) return RK_EINVAL;
+  HIP_TRY(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+  uint64_t cnt = 0;
+  double ms = 0;
+  for (auto &ev : ctx->prof_events) {
+    if (kernel != 3 && ev.kind != kernel) continue;
+    HIP_TRY(ctx, hipEventSynchronize(ev.b), "hipEventSynchronize");
+    float t = 0;
+    HIP_TRY(ctx, hipEventElapsedTime(&t, ev.a, ev.b), "hipEventElapsedTime");
+    ms += t;
+    ++cnt;
+  }
+  if (launches) *launches = cnt;
+  if (total_ms) *total_ms = ms;
+  return RK_OK;
+}
+
+rk_status rk_ctx_profile_reset(rk_ctx *ctx) {
+  if (!ctx) return RK_EINVAL;
+  hipSetDevice(ctx->device);
+  for (auto &ev : ctx->prof_events) {
+    hipEventSynchronize(ev.b);
+    ctx->free_events.push_back(ev);
+  }
+  ctx->prof_events.clear();
+  return RK_OK;
+}
+
+}  // extern "C"

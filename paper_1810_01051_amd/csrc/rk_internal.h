@@ -1,0 +1,109 @@
+// Internal layouts shared by the host runtime and the HIP kernels of librk.
+//
+// Text windows are identified by their END byte e (window = T[e-m+1 .. e]):
+// a tile owns the windows whose last byte falls inside it, so every thread
+// ingests its own bytes at static register positions and the (m-1)-byte
+// halo sits in front of the tile.  Start position x = e - m + 1.
+#pragma once
+#include <stdint.h>
+
+namespace rk {
+
+constexpr uint64_t kQ = (1ull << 61) - 1;  // Mersenne modulus 2^61 - 1
+constexpr uint32_t kFront = 64;            // halo bytes kept in front of a tile (>= RK_MAX_M)
+constexpr uint32_t kPosBits = 40;          // hit record = pid << 40 | start position
+constexpr uint64_t kPosMask = (1ull << kPosBits) - 1;
+constexpr uint32_t kCandCap = 1024;        // candidate slots in LDS per workgroup
+constexpr uint32_t kMaxWaves = 16;
+constexpr uint32_t kNoLink = 0xFFFFFFFFu;
+constexpr uint64_t kEmptyKey = ~0ull;      // empty exact-table slot (no canonical hash is >= q)
+
+// Screen/test variants of one bucket (one pattern length inside one instance).
+enum BucketKind : uint32_t {
+  kListScreen = 0,   // screen mode: shift-add hash compared with up to 4 targets
+  kTableScreen = 1,  // screen mode: shift-add hash probed in the LDS fingerprint table
+  kListExact = 2,    // exact mode: lazy 61-bit state compared with up to 4 lazy targets
+  kTableExact = 3,   // exact mode: canonical 61-bit hash probed in the fingerprint table
+  kDump = 4,         // exact rolling state written out for sampled windows (no patterns)
+};
+
+// Bucket descriptor as laid out in an instance image (64 bytes).
+struct BucketDesc {
+  uint32_t m;          // pattern length
+  uint32_t kind;       // BucketKind
+  uint32_t shift;      // screen shift s in {1,2,4,8} (screen kinds)
+  uint32_t mask;       // screen-hash mask (all ones unless m < 4 with s = 8)
+  uint32_t tgt[4];     // list kinds: targets (padded by repetition)
+  uint32_t fp_off;     // table kinds: byte offset of the fingerprint table (u32 slots)
+  uint32_t fp_mask;    // fingerprint slots - 1
+  uint32_t ex_off;     // byte offset of exact keys (u64[ex_mask+1]), then heads (u32[ex_mask+1])
+  uint32_t ex_mask;    // exact-table slots - 1
+  uint32_t link_off;   // byte offset of u32[npat]: next local index with the same hash
+  uint32_t pid_off;    // byte offset of u32[npat]: global pattern id
+  uint32_t pat_off;    // byte offset of pattern bytes, local pattern i at pat_off + i*m
+  uint32_t npat;       // patterns in this bucket
+};
+static_assert(sizeof(BucketDesc) == 64, "bucket descriptor is 64 bytes");
+
+// Header at the start of an instance image (16 bytes), followed by nb descriptors.
+struct ImageHeader {
+  uint32_t nbuckets;
+  uint32_t bytes;      // total image bytes (multiple of 16)
+  uint32_t max_m;
+  uint32_t pad;
+};
+
+// One instance of a scan job (48 bytes).
+struct InstDesc {
+  const uint8_t *text; // 16-byte aligned
+  uint64_t n;
+  uint64_t tile_base;  // global id of this instance's tile 0
+  uint64_t ntiles;
+  uint32_t img_off;    // byte offset of the instance image in the plan blob (16-aligned)
+  uint32_t img_bytes;
+  uint64_t pad;
+};
+static_assert(sizeof(InstDesc) == 48, "instance descriptor is 48 bytes");
+
+// Kernel parameters of the scan (passed by value).
+struct ScanParams {
+  const InstDesc *inst;
+  uint32_t ninst;
+  uint32_t img_cap;           // LDS bytes reserved for an instance image
+  const uint8_t *blob;        // instance images
+  const uint64_t *items;      // item -> global tile id (nullptr: identity)
+  uint64_t nitems;
+  const uint32_t *nitems_dev; // optional device-side bound on nitems (rescan list length)
+  uint32_t *tile_counts;      // hits per global tile
+  uint64_t *out;              // count mode: slabs [tile][slab_cap]; direct mode: compact array
+  const uint64_t *tile_offsets; // direct mode: first output slot of each tile
+  uint32_t slab_cap;
+  uint32_t direct;            // 1: rescan writing every hit at tile_offsets[tile]
+  unsigned long long *total;  // count mode: hits over all tiles
+  uint32_t *ovf_count;        // count mode: number of tiles with more hits than slab_cap
+  uint64_t *ovf_list;         // count mode: those tiles' global ids
+  uint32_t *queue;            // atomic work-queue cursor (nullptr: static striding)
+  uint32_t grab;              // items taken per queue pop
+  uint64_t *dump_out;         // kDump buckets: destination of sampled hashes
+  uint64_t dump_stride;
+  uint64_t dump_cap;
+};
+
+// Host-side geometry table (workgroup size, windows per thread).
+struct TileCfg {
+  uint32_t wg;
+  uint32_t c;
+};
+constexpr int kNumTileCfg = 4;
+constexpr TileCfg kTileCfgs[kNumTileCfg] = {{256, 68}, {256, 132}, {512, 68}, {256, 36}};
+
+// Kernel families: each scan kernel is compiled for the bucket kinds one plan
+// can hold, so that a single-pattern search does not pay the register budget
+// of the multi-pattern and exact variants.
+enum Family : int {
+  kFamScreen1 = 0,  // list screen with one target per bucket
+  kFamScreen = 1,   // every screen kind
+  kFamExact = 2,    // every exact kind and the hash dump
+};
+
+}  // namespace rk

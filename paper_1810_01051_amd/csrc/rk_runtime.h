@@ -1,0 +1,135 @@
+// Host-side objects of librk (context, plan, scratch layout) and the launch
+// functions exported by the device translation unit.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/rk.h"
+#include "rk_internal.h"
+
+namespace rk {
+
+constexpr uint32_t kImgLimit = 64 * 1024;  // largest instance image staged in LDS
+
+struct ProfEvent {
+  hipEvent_t a, b;
+  int kind;  // 0 scan, 1 rescan, 2 collect
+};
+
+struct CountMemo {
+  const void *scratch = nullptr;
+  const rk_plan *plan = nullptr;
+  uint64_t n = 0;
+  uint64_t total = 0;
+};
+
+struct VInst {
+  uint32_t src;       // real instance index
+  uint32_t img_off;   // in the plan blob
+  uint32_t img_bytes;
+  uint32_t nbuckets = 0;
+  uint32_t max_m = 0;
+  bool only_one_list = true;  // every bucket is a list screen with one target
+};
+
+struct RealInst {
+  const uint8_t *text;
+  uint64_t n;
+  uint32_t pid_base;
+  uint32_t k;
+};
+
+}  // namespace rk
+
+struct rk_ctx {
+  int device = 0;
+  int num_cu = 0;
+  std::string arch;
+  std::string err;
+  uint32_t slab_cap = 0;
+  int tile_cfg = -1;
+  uint32_t grid = 0;
+  bool profile = false;
+  int queue = -1;
+  uint64_t *pinned = nullptr;  // 4 KiB of pinned host memory for small transfers
+  std::vector<uint8_t> upload; // staging for instance descriptors
+  std::vector<rk::ProfEvent> prof_events, free_events;
+  int tune[3][RK_MAX_M + 1];
+  uint8_t tune_measured[3][RK_MAX_M + 1] = {};
+  rk::CountMemo memo[16];
+  uint32_t memo_next = 0;
+  void *dump_dev = nullptr;    // device copy of the dump image
+};
+
+struct rk_plan {
+  int device = 0;
+  int mode = RK_MODE_SCREEN;
+  bool batch = false;
+  int cfg = 0;
+  int fam = rk::kFamScreen1;
+  uint32_t k_total = 0;
+  uint32_t img_cap = 0;       // LDS bytes reserved for images (max image size)
+  uint64_t text_bytes = 0;
+  std::vector<rk::RealInst> insts;
+  std::vector<rk::VInst> vinsts;
+  void *dev = nullptr;        // one device allocation: blob | instance descs | items
+  uint8_t *blob_dev = nullptr;
+  rk::InstDesc *inst_dev = nullptr;  // batch: fixed descriptors (sorted by tile_base)
+  uint64_t *items_dev = nullptr;     // batch: queue order of global tile ids
+  uint64_t total_tiles = 0;          // batch
+  uint64_t nitems = 0;               // batch
+};
+
+namespace rk {
+
+struct Layout {
+  uint64_t T = 0;      // tiles
+  uint64_t T1 = 0;     // tiles per virtual instance (single plans)
+  uint32_t S = 0;      // slab slots per tile
+  uint32_t W = 0;      // tile bytes
+  uint64_t ctr = 0, inst = 0, counts = 0, offsets = 0, ovf = 0, tmp = 0, slabs = 0, total = 0;
+};
+
+rk_status set_err(rk_ctx *ctx, rk_status st, const char *fmt, ...);
+rk_status hip_err(rk_ctx *ctx, hipError_t e, const char *what);
+inline rk_status hip_err_or_ok(rk_ctx *ctx, hipError_t e) {
+  return e == hipSuccess ? RK_OK : hip_err(ctx, e, "profiling event");
+}
+uint64_t host_hash(const uint8_t *p, uint64_t m);
+uint32_t screen_shift(uint32_t m);
+uint32_t screen_hash(const uint8_t *p, uint32_t m);
+
+rk_status plan_build(rk_ctx *ctx, const rk_instance *inst, uint32_t count, int mode, bool batch, rk_plan **out);
+rk_status make_layout(rk_ctx *ctx, const rk_plan *plan, uint64_t n, Layout &L);
+uint64_t work_bytes_for(const rk_plan *plan, uint64_t total);
+rk_status count_enqueue(rk_ctx *ctx, const rk_plan *plan, const uint8_t *text, uint64_t n, void *scratch,
+                        uint64_t scratch_bytes, hipStream_t s);
+rk_status count_finish(rk_ctx *ctx, const rk_plan *plan, void *scratch, hipStream_t s, uint64_t *total);
+rk_status collect_enqueue(rk_ctx *ctx, const rk_plan *plan, const uint8_t *text, uint64_t n, void *scratch,
+                          uint64_t scratch_bytes, void *work, uint64_t work_bytes, uint64_t *offsets,
+                          uint64_t *positions, uint64_t capacity, hipStream_t s);
+
+// device translation unit
+uint32_t scan_lds_bytes(int cfg, uint32_t img_cap);
+hipError_t launch_scan(int cfg, int fam, const ScanParams &p, uint32_t grid, uint32_t lds_bytes, hipStream_t s);
+hipError_t scan_occupancy(int cfg, int fam, uint32_t lds_bytes, int *blocks_per_cu);
+uint64_t scan_tmp_words(uint64_t n);
+hipError_t launch_exclusive_scan(const uint32_t *in, uint64_t n, uint64_t *out, uint64_t *tmp, uint64_t *total_dev,
+                                 hipStream_t s);
+hipError_t launch_compact(const uint32_t *counts, const uint64_t *offs, uint64_t ntiles, const uint64_t *slabs,
+                          uint32_t slab_cap, uint64_t *out, hipStream_t s);
+uint64_t radix_blocks(uint64_t n);
+hipError_t launch_radix(uint64_t *a, uint64_t *b, uint64_t n, uint32_t npass, uint32_t *ghist, uint64_t *goff,
+                        uint64_t *tmp, uint64_t **result, hipStream_t s);
+hipError_t launch_pid_offsets(const uint64_t *sorted, uint64_t n, uint32_t k, uint64_t *offsets, hipStream_t s);
+hipError_t launch_strip(const uint64_t *rec, uint64_t n, uint64_t *pos, hipStream_t s);
+hipError_t launch_single_offsets(uint64_t *offsets, uint64_t total, hipStream_t s);
+hipError_t launch_window_hashes(const uint8_t *text, uint64_t n, uint32_t m, const uint64_t *xs, uint64_t cnt,
+                                uint64_t *out, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t *p, uint64_t words, uint32_t v, hipStream_t s);
+rk_status tune_run(rk_ctx *ctx, uint64_t n, const uint32_t *lengths, uint32_t nl, const char *path);
+rk_status tune_load(rk_ctx *ctx, const char *path);
+
+}  // namespace rk

@@ -35,6 +35,9 @@ def iid_text(g: np.random.Generator, n: int, alphabet: np.ndarray) -> np.ndarray
         e = min(n, s + _GEN_CHUNK)
         if a == 256:
             out[s:e] = np.frombuffer(g.bytes(e - s), dtype=np.uint8)
+        elif a & (a - 1) == 0:  # power-of-two alphabet: low bits of raw random bytes
+            table = bytes(int(alphabet[i & (a - 1)]) for i in range(256))
+            out[s:e] = np.frombuffer(g.bytes(e - s).translate(table), dtype=np.uint8)
         else:
             out[s:e] = alphabet[g.integers(0, a, size=e - s, dtype=np.uint8)]
     return out

@@ -1,0 +1,273 @@
+"""GPU parity: librk (through its C ABI) against the CPU oracle, element by
+element, on seeded inputs.  Integer results, so the bar is exact equality."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+import rkgen
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+Q = (1 << 61) - 1
+MODES = ["screen", "exact"]
+
+
+@pytest.fixture(scope="module")
+def rk():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1810_01051_amd as rk
+    return rk
+
+
+@pytest.fixture(scope="module")
+def ctx(rk):
+    c = rk.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a):
+    if isinstance(a, (bytes, bytearray)):
+        a = np.frombuffer(bytes(a), dtype=np.uint8)
+    t = torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint8).copy()).to("cuda:0")
+    if t.numel() == 0:
+        t = torch.empty(0, dtype=torch.uint8, device="cuda:0")
+    return t
+
+
+def run(ctx, rk, text_np, pats, mode, opts=None):
+    opts = opts or {}
+    text = dev(text_np)
+    for k, v in opts.items():
+        ctx.set_option(k, v)
+    try:
+        plan = rk.Plan(ctx, pats, mode)
+        off, pos = plan.search(text)
+        torch.cuda.synchronize()
+        plan.close()
+    finally:
+        for k in opts:
+            ctx.set_option(k, {1: 0, 2: -1, 3: 0, 4: 0, 5: -1}[k])
+    return off.cpu().numpy().astype(np.uint64), pos.cpu().numpy().astype(np.uint64)
+
+
+def assert_same(got, ref, label=""):
+    go, gp = got
+    ro, rp = ref
+    assert go.tolist() == ro.tolist(), "offsets differ %s" % label
+    if gp.tolist() != rp.tolist():
+        lists_g = oracle.split(go, gp)
+        lists_r = oracle.split(ro, rp)
+        for j, (a, b) in enumerate(zip(lists_g, lists_r)):
+            if a.tolist() != b.tolist():
+                extra = sorted(set(a.tolist()) - set(b.tolist()))[:5]
+                miss = sorted(set(b.tolist()) - set(a.tolist()))[:5]
+                raise AssertionError("pattern %d differs %s: extra %s missing %s" % (j, label, extra, miss))
+        raise AssertionError("positions differ %s" % label)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_config1_full(ctx, rk, mode):
+    s = rkgen.config1()
+    got = run(ctx, rk, s.text, s.patterns, mode)
+    ref = oracle.search(s.text, s.patterns)
+    assert int(ref[0][-1]) == 101
+    assert_same(got, ref, "config1 " + mode)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_config2_reduced(ctx, rk, mode):
+    s = rkgen.config2(n=(1 << 23) + 77, plants=300)
+    got = run(ctx, rk, s.text, s.patterns, mode)
+    ref = oracle.search(s.text, s.patterns, threads=4)
+    assert int(ref[0][-1]) == 300
+    assert_same(got, ref, "config2 " + mode)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_config3_reduced_multi(ctx, rk, mode):
+    s = rkgen.config3(n=(1 << 22) + 5, k=256, sampled=128)
+    got = run(ctx, rk, s.text, s.patterns, mode)
+    ref = oracle.search(s.text, s.patterns, threads=4)
+    assert int(ref[0][-1]) > 1000
+    assert_same(got, ref, "config3 " + mode)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_random_small(ctx, rk, mode):
+    g = rkgen.rng(50, 1 if mode == "screen" else 2)
+    tables = [np.frombuffer(b"ab", np.uint8), rkgen.ACGT, rkgen.LOWER, rkgen.BYTE256]
+    for trial in range(40):
+        n = int(g.integers(0, 6000))
+        table = tables[trial % 4]
+        text = rkgen.iid_text(g, n, table)
+        k = int(g.integers(0, 10))
+        pats = []
+        for _ in range(k):
+            m = int(g.integers(1, 65))
+            if n >= m and g.random() < 0.7:
+                o = int(g.integers(0, n - m + 1))
+                pats.append(text[o:o + m].tobytes())
+            else:
+                pats.append(rkgen.iid_text(g, m, table).tobytes())
+        got = run(ctx, rk, text, pats, mode)
+        assert_same(got, oracle.search(text, pats), "trial %d n=%d" % (trial, n))
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3])
+def test_tile_seams_every_geometry(ctx, rk, mode, cfg):
+    """Occurrences planted across tile and thread seams, first and last window."""
+    lib = rk._lib.load()
+    wg, c, tb = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
+    lib.rk_tile_cfg(cfg, ctypes.byref(wg), ctypes.byref(c), ctypes.byref(tb))
+    W, C = tb.value, c.value
+    g = rkgen.rng(51, cfg)
+    n = 3 * W + 40
+    text = rkgen.iid_text(g, n, rkgen.ACGT)
+    pats = [rkgen.ACGT[g.integers(0, 4, size=m)].tobytes() for m in (1, 3, 4, 7, 16, 31, 32, 33, 63, 64)]
+    for j, p in enumerate(pats):
+        m = len(p)
+        for base in (0, W, 2 * W, 3 * W, C, W + 5 * C, n - m):
+            for d in (-m, -m + 1, -1, 0, 1):
+                x = base + d
+                if 0 <= x <= n - m:
+                    text[x:x + m] = np.frombuffer(p, np.uint8)
+    got = run(ctx, rk, text, pats, mode, {rk._lib.RK_OPT_TILE_CFG: cfg})
+    assert_same(got, oracle.search(text, pats), "cfg %d" % cfg)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_edge_cases(ctx, rk, mode):
+    cases = [
+        (b"abcab", [b"ab"]),
+        (b"abc", [b"abc", b"abcd"]),
+        (b"aaaa", [b"aa", b"a"]),
+        (b"\x00\xff\x00\xff\x00", [b"\x00\xff", b"\xff\x00\xff"]),
+        (b"xyxyx", [b"yx", b"yx"]),
+        (b"abc", []),
+        (b"", [b"a"]),
+        (b"a" * 5000, [b"a" * 64, b"a" * 33, b"a"]),
+        (b"\x00" * 3000, [b"\x00" * 9, b"\x00\x01"]),
+    ]
+    for text, pats in cases:
+        got = run(ctx, rk, np.frombuffer(text, np.uint8), pats, mode)
+        assert_same(got, oracle.search(text, pats), repr((text[:10], pats[:2])))
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_constructed_collisions_are_rejected(ctx, rk, mode):
+    """Windows with the pattern's d=256 hash but other bytes are not reported,
+    and the scan's own rolling hashes of both windows are equal."""
+    g = rkgen.rng(52, 0)
+    text = rkgen.iid_text(g, 100000, rkgen.LOWER)
+    pats = []
+    for m in (9, 16, 40, 64):
+        w = bytearray(rkgen.LOWER[g.integers(8, 18, size=m)].tobytes())
+        w2 = bytearray(w)
+        w2[0] += 1
+        w2[8] -= 8
+        assert oracle.hash(bytes(w)) == oracle.hash(bytes(w2))
+        for x in range(1000 * m, 1000 * m + 10 * m, m):
+            text[x:x + m] = np.frombuffer(bytes(w2), np.uint8)
+        text[200 * m:200 * m + m] = np.frombuffer(bytes(w), np.uint8)
+        pats.append(bytes(w))
+    got = run(ctx, rk, text, pats, mode)
+    ref = oracle.search(text, pats)
+    assert_same(got, ref, "collisions")
+    assert int(ref[0][-1]) == len(pats)
+    # the dumped rolling hashes of w and w2 windows agree
+    t = dev(text)
+    for w in pats:
+        m = len(w)
+        d = ctx.scan_dump(t, m, m).cpu().numpy().astype(np.uint64)
+        assert d[200] == d[1000] == np.uint64(oracle.hash(w))
+
+
+@pytest.mark.parametrize("m", [1, 4, 7, 8, 9, 15, 16, 24, 31, 32, 33, 47, 61, 63, 64])
+def test_scan_dump_matches_oracle(ctx, rk, m):
+    g = rkgen.rng(53, m)
+    n = 300000 + m
+    text = np.frombuffer(g.bytes(n), np.uint8).copy()
+    stride = 4099
+    d = ctx.scan_dump(dev(text), m, stride).cpu().numpy().astype(np.uint64)
+    xs = np.arange(0, n - m + 1, stride, dtype=np.uint64)
+    assert d.tolist() == oracle.window_hashes(text, m, xs).tolist()
+
+
+def test_window_hashes_match_oracle(ctx, rk):
+    g = rkgen.rng(54, 0)
+    n = 100000
+    text = np.frombuffer(g.bytes(n), np.uint8).copy()
+    t = dev(text)
+    for m in (1, 8, 9, 32, 64, 100, 800):
+        xs = np.unique(g.integers(0, n - m + 1, size=500)).astype(np.int64)
+        got = ctx.window_hashes(t, m, torch.from_numpy(xs)).cpu().numpy().astype(np.uint64)
+        assert got.tolist() == oracle.window_hashes(text, m, xs.astype(np.uint64)).tolist()
+    bad = ctx.window_hashes(t, 10, torch.tensor([n - 9, n], dtype=torch.int64)).cpu().numpy()
+    assert (bad.astype(np.uint64) == np.uint64(2**64 - 1)).all()
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_slab_overflow_rescan(ctx, rk, mode):
+    """A one-slot staging slab forces every tile with hits through the rescan."""
+    s = rkgen.config3(n=1 << 20, k=64, sampled=48)
+    got = run(ctx, rk, s.text, s.patterns, mode, {rk._lib.RK_OPT_SLAB_CAP: 1})
+    assert_same(got, oracle.search(s.text, s.patterns, threads=4), "slab=1")
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_queue_and_grid_options(ctx, rk, mode):
+    s = rkgen.config2(n=(1 << 21) + 3, plants=100)
+    ref = oracle.search(s.text, s.patterns)
+    for opts in ({rk._lib.RK_OPT_QUEUE: 1}, {rk._lib.RK_OPT_GRID: 7}, {rk._lib.RK_OPT_QUEUE: 1,
+                                                                        rk._lib.RK_OPT_GRID: 3}):
+        assert_same(run(ctx, rk, s.text, s.patterns, mode, opts), ref, str(opts))
+
+
+def test_errors(ctx, rk):
+    RkError = rk._lib.RkError
+    with pytest.raises(RkError) as e:
+        rk.Plan(ctx, [b""])
+    assert e.value.status == rk._lib.RK_EINVAL
+    with pytest.raises(RkError) as e:
+        rk.Plan(ctx, [b"a" * 65])
+    assert e.value.status == rk._lib.RK_EUNSUPPORTED
+    text = dev(np.zeros(4096, np.uint8))
+    plan = rk.Plan(ctx, [b"\x00\x00"])
+    with pytest.raises(RkError) as e:
+        plan.count(text[1:])
+    assert e.value.status == rk._lib.RK_EINVAL
+    total = plan.count(text)
+    assert total == 4095
+    with pytest.raises(RkError) as e:
+        plan.collect(text, total, out=(torch.empty(2, dtype=torch.int64, device="cuda:0"),
+                                       torch.empty(10, dtype=torch.int64, device="cuda:0")))
+    assert e.value.status == rk._lib.RK_ENOSPACE
+    small = torch.empty(16, dtype=torch.uint8, device="cuda:0")
+    with pytest.raises(RkError) as e:
+        plan.count(text, scratch=small)
+    assert e.value.status == rk._lib.RK_ENOSPACE
+    plan.close()
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_batch_matches_solo_and_oracle(ctx, rk, mode):
+    insts = rkgen.config4(count=24, lmax=1 << 18)
+    texts = [dev(s.text) for s in insts]
+    bp = rk.BatchPlan(ctx, texts, [s.patterns for s in insts], mode)
+    off, pos = bp.search()
+    torch.cuda.synchronize()
+    per = bp.split(off, pos)
+    for i, s in enumerate(insts):
+        ro, rp = oracle.search(s.text, s.patterns)
+        ref = oracle.split(ro, rp)
+        for j in range(len(s.patterns)):
+            assert per[i][j].astype(np.uint64).tolist() == ref[j].tolist(), (i, j)
+        solo = run(ctx, rk, s.text, s.patterns, mode)
+        assert_same(solo, (ro, rp), "solo %d" % i)
+    bp.close()
