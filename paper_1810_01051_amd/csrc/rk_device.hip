@@ -125,6 +125,19 @@ __device__ __forceinline__ void pass_list_screen(const uint32_t *tw, uint32_t ms
   uint32_t h = 0, acc = 0;
 #pragma unroll
   for (int j = 64 - WU; j < 64; ++j) h = (h << S) + byte_at(w, j);
+  if (ANY && NT == 1) {
+    // one target: the minimum of h ^ target over the windows is zero iff
+    // some window matches; no per-window scalar work
+    uint32_t mn = 0xFFFFFFFFu;
+#pragma unroll
+    for (int i = 0; i < C; ++i) {
+      h = (h << S) + byte_at(w, 64 + i);
+      const uint32_t v = (S == 8) ? (h & msk) : h;
+      mn = min(mn, v ^ tg[0]);
+    }
+    any_or(any, ballot(mn == 0u));
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < C; ++i) {
     h = (h << S) + byte_at(w, 64 + i);
@@ -360,7 +373,7 @@ __device__ __forceinline__ bool bytes_equal(const uint8_t *a, const uint8_t *b, 
 //
 // LDS: [tile: kFront + W + 16][cand: kCandCap u32][misc: 64 u32][image: img_cap]
 template <int WG, int C, int FAM>
-__global__ __launch_bounds__(WG) void scan_kernel(ScanParams p) {
+__global__ __launch_bounds__(WG, 4) void scan_kernel(ScanParams p) {
   constexpr uint32_t W = WG * C;
   constexpr uint32_t TILE_LDS = (kFront + W + 16 + 15) & ~15u;
   constexpr uint32_t NCH = (kFront + W) / 16;  // 16-byte chunks loaded per tile
@@ -375,66 +388,87 @@ __global__ __launch_bounds__(WG) void scan_kernel(ScanParams p) {
   const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   uint32_t cur_inst = kNoLink;
   uint64_t static_item = blockIdx.x;
-  uint64_t grab_next = 0, grab_left = 0;
   uint32_t flag_parity = 0;
   const uint64_t nitems = p.nitems_dev ? min(p.nitems, (uint64_t)*p.nitems_dev) : p.nitems;
 
-  for (;;) {
-    uint64_t item;
+  // Next work item (uniform across the workgroup).  With a queue, thread 0
+  // pops and the value is read back after the barrier that follows.
+  auto pop = [&]() -> uint64_t {
     if (p.queue) {
-      if (grab_left == 0) {
-        __syncthreads();
-        if (tid == 0) misc[48] = atomicAdd(p.queue, p.grab);
-        __syncthreads();
-        grab_next = misc[48];
-        grab_left = p.grab;
-      }
-      item = grab_next++;
-      --grab_left;
-    } else {
-      item = static_item;
-      static_item += gridDim.x;
+      __syncthreads();
+      if (tid == 0) misc[48] = atomicAdd(p.queue, 1u);
+      __syncthreads();
+      return misc[48];
     }
-    if (item >= nitems) break;
-    const uint64_t gt = p.items ? p.items[item] : item;
-
-    // instance owning global tile gt
-    uint32_t lo = 0, hi = p.ninst;
+    const uint64_t it = static_item;
+    static_item += gridDim.x;
+    return it;
+  };
+  struct Item {
+    uint64_t gt;
+    uint32_t inst;
+    const uint8_t *text;
+    uint64_t n;
+    int64_t tstart;
+  };
+  auto locate = [&](uint64_t item) -> Item {
+    Item it;
+    it.gt = p.items ? p.items[item] : item;
+    uint32_t lo = 0, hi = p.ninst;  // instance owning global tile gt
     while (hi - lo > 1) {
       const uint32_t mid = (lo + hi) >> 1;
-      if (p.inst[mid].tile_base <= gt) lo = mid;
+      if (p.inst[mid].tile_base <= it.gt) lo = mid;
       else hi = mid;
     }
-    const uint8_t *text = p.inst[lo].text;
-    const uint64_t n = p.inst[lo].n;
-    const uint64_t lt = gt - p.inst[lo].tile_base;
-    const int64_t tstart = (int64_t)(lt * W);
-
-    __syncthreads();  // previous tile finished with tile / cand / image
-    if (lo != cur_inst) {
-      const uint4 *src = (const uint4 *)(p.blob + p.inst[lo].img_off);
-      uint4 *dst = (uint4 *)img;
-      const uint32_t nq = p.inst[lo].img_bytes / 16u;
-      for (uint32_t q = tid; q < nq; q += WG) dst[q] = src[q];
-      cur_inst = lo;
+    it.inst = lo;
+    it.text = p.inst[lo].text;
+    it.n = p.inst[lo].n;
+    it.tstart = (int64_t)((it.gt - p.inst[lo].tile_base) * W);
+    return it;
+  };
+  // text bytes [tstart - kFront, tstart + W) in aligned 16-byte chunks
+  uint4 v[LOADS];
+  auto issue_loads = [&](const Item &it) {
+#pragma unroll
+    for (uint32_t u = 0; u < LOADS; ++u) {
+      const uint32_t q = tid + u * WG;
+      const int64_t g = it.tstart - (int64_t)kFront + 16 * (int64_t)q;
+      v[u] = make_uint4(0, 0, 0, 0);
+      if (q < NCH && g >= 0 && (uint64_t)g < it.n) v[u] = *(const uint4 *)(it.text + g);
     }
-    // tile load: text bytes [tstart - kFront, tstart + W) in aligned 16-byte chunks
-    {
-      uint4 v[LOADS];
+  };
+
+  uint64_t item = pop();
+  Item cur;
+  if (item < nitems) {
+    cur = locate(item);
+    issue_loads(cur);
+  }
+  while (item < nitems) {
+    const uint64_t next = pop();  // ends with a barrier when a queue is used
+    __syncthreads();  // previous tile finished with tile / cand / image
+    if (cur.inst != cur_inst) {
+      const uint4 *src = (const uint4 *)(p.blob + p.inst[cur.inst].img_off);
+      uint4 *dst = (uint4 *)img;
+      const uint32_t nq = p.inst[cur.inst].img_bytes / 16u;
+      for (uint32_t q = tid; q < nq; q += WG) dst[q] = src[q];
+      cur_inst = cur.inst;
+    }
 #pragma unroll
-      for (uint32_t u = 0; u < LOADS; ++u) {
-        const uint32_t q = tid + u * WG;
-        const int64_t g = tstart - (int64_t)kFront + 16 * (int64_t)q;
-        v[u] = make_uint4(0, 0, 0, 0);
-        if (q < NCH && g >= 0 && (uint64_t)g < n) v[u] = *(const uint4 *)(text + g);
-      }
-#pragma unroll
-      for (uint32_t u = 0; u < LOADS; ++u) {
-        const uint32_t q = tid + u * WG;
-        if (q < NCH) *(uint4 *)(tile + 16 * q) = v[u];
-      }
+    for (uint32_t u = 0; u < LOADS; ++u) {
+      const uint32_t q = tid + u * WG;
+      if (q < NCH) *(uint4 *)(tile + 16 * q) = v[u];
     }
     __syncthreads();
+    // the next tile's loads are in flight while this one is processed
+    Item nx;
+    if (next < nitems) {
+      nx = locate(next);
+      issue_loads(nx);
+    }
+    const uint64_t gt = cur.gt;
+    const uint64_t n = cur.n;
+    const int64_t tstart = cur.tstart;
 
     // this thread's bytes: 64 before its first window end, then C
     const uint32_t *tw = (const uint32_t *)(tile + kFront + tid * C - 64);
@@ -579,6 +613,8 @@ __global__ __launch_bounds__(WG) void scan_kernel(ScanParams p) {
         p.ovf_list[o] = gt;
       }
     }
+    item = next;
+    cur = nx;
   }
 }
 

@@ -335,6 +335,7 @@ rk_status count_enqueue(rk_ctx *ctx, const rk_plan *plan, const uint8_t *text, u
   mm.plan = plan;
   mm.n = n;
   mm.total = ~0ull;  // filled by count_finish
+  mm.overflow = 0xFFFFFFFFu;
   return RK_OK;
 }
 
@@ -344,8 +345,12 @@ rk_status count_finish(rk_ctx *ctx, const rk_plan *plan, void *scratch, hipStrea
   e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_err(ctx, e, "scan");
   *total = ctx->pinned[0];
+  const uint32_t ovf = (uint32_t)(ctx->pinned[1] & 0xFFFFFFFFu);
   for (auto &mm : ctx->memo)
-    if (mm.scratch == scratch && mm.plan == plan) mm.total = *total;
+    if (mm.scratch == scratch && mm.plan == plan) {
+      mm.total = *total;
+      mm.overflow = ovf;
+    }
   return RK_OK;
 }
 
@@ -362,8 +367,12 @@ rk_status collect_enqueue(rk_ctx *ctx, const rk_plan *plan, const uint8_t *text,
   uint8_t *sc = (uint8_t *)scratch;
   // total of the matching count pass
   uint64_t total = ~0ull;
+  uint32_t overflow = 0xFFFFFFFFu;
   for (auto &mm : ctx->memo)
-    if (mm.scratch == scratch && mm.plan == plan && mm.n == n && mm.total != ~0ull) total = mm.total;
+    if (mm.scratch == scratch && mm.plan == plan && mm.n == n && mm.total != ~0ull) {
+      total = mm.total;
+      overflow = mm.overflow;
+    }
   hipError_t e;
   if (total == ~0ull) {
     e = hipMemcpyAsync(ctx->pinned, sc + L.ctr, 8, hipMemcpyDeviceToHost, s);
@@ -403,8 +412,9 @@ rk_status collect_enqueue(rk_ctx *ctx, const rk_plan *plan, const uint8_t *text,
   if (e != hipSuccess) return hip_err(ctx, e, "compact");
   e = prof_end(ctx, s, slot);
   if (e != hipSuccess) return hip_err(ctx, e, "profiling event");
-  // rescan of tiles whose hits did not fit their slab (count read on the device)
-  {
+  // rescan of tiles whose hits did not fit their slab (count read on the device;
+  // skipped when the count pass reported none)
+  if (overflow != 0) {
     ScanParams p;
     base_params(plan, L, sc, p);
     p.items = (const uint64_t *)(sc + L.ovf);

@@ -23,6 +23,7 @@ struct CountMemo {
   const rk_plan *plan = nullptr;
   uint64_t n = 0;
   uint64_t total = 0;
+  uint32_t overflow = 0xFFFFFFFFu;  // tiles whose hits did not fit their slab (unknown: all ones)
 };
 
 struct VInst {
