@@ -135,6 +135,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-exact", action="store_true", help="skip the every-window exact-hash measurement")
     ap.add_argument("--tune", default=os.path.join(ROOT, "profiles", "autotune_gfx950.json"))
+    ap.add_argument("--cfg", type=int, default=-1, help="force a scan geometry (rk_tile_cfg index)")
+    ap.add_argument("--grid", type=int, default=0, help="force the persistent grid size")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (for PMC byte-counter calibration)")
     args = ap.parse_args()
@@ -170,6 +172,11 @@ def main():
     ctx = rk.Context(0)
     if args.tune and os.path.exists(args.tune):
         ctx.autotune_load(args.tune)
+    from paper_1810_01051_amd import _lib
+    if args.cfg >= 0:
+        ctx.set_option(_lib.RK_OPT_TILE_CFG, args.cfg)
+    if args.grid > 0:
+        ctx.set_option(_lib.RK_OPT_GRID, args.grid)
 
     res = run_mode(rk, ctx, text, pattern, args.mode, args.steps, args.warmup)
     log("%s: %.3f ms/step, scan %.3f ms" % (args.mode, res["ms_per_step"], res["scan_ms"]))

@@ -111,7 +111,8 @@ rk_status rk_tile_cfg(int i, uint32_t *wg, uint32_t *windows_per_thread, uint32_
 
 /* Accumulated device time of scan launches since profiling was switched on.
  * kernel: 0 = scan (count pass), 1 = rescan of overflowed tiles, 2 = collect
- * (compaction + sort), 3 = all.  Synchronises the context's device. */
+ * (compaction + sort), 3 = all, 4 = rk_stream_read.  Synchronises the
+ * context's device. */
 rk_status rk_ctx_profile(rk_ctx *ctx, int kernel, uint64_t *launches, double *total_ms);
 rk_status rk_ctx_profile_reset(rk_ctx *ctx);
 
@@ -168,6 +169,13 @@ rk_status rk_window_hashes(rk_ctx *ctx, const uint8_t *text_dev, uint64_t n, uin
  * cap = entries of out_dev (RK_ENOSPACE if below cnt). */
 rk_status rk_scan_dump(rk_ctx *ctx, const uint8_t *text_dev, uint64_t n, uint32_t m,
                        uint64_t stride, uint64_t *out_dev, uint64_t cap, rk_stream s);
+
+/* Read-bandwidth ceiling for the scan's roofline: reads data_dev[0..n) once
+ * with coalesced 16-byte loads (grid workgroups of 256 threads, grid-stride)
+ * and writes one XOR-fold word per workgroup to out_dev[0..grid).  data_dev
+ * 16-byte aligned, n a multiple of 16.  Timed by RK_OPT_PROFILE as kernel 4. */
+rk_status rk_stream_read(rk_ctx *ctx, const void *data_dev, uint64_t n, uint32_t *out_dev, uint32_t grid,
+                         rk_stream s);
 
 /* ----------------------------------------------------------------- batching */
 

@@ -1,0 +1,97 @@
+/*
+ * rk_server.h -- continuous-batching search server of librk.
+ *
+ * Corpora stay resident in device memory.  Clients submit searches (a corpus
+ * id and a pattern set, the problem of Sec. 1 of Shah & Oza: every occurrence
+ * of every pattern) from any thread.  A scheduler thread forms steps from the
+ * requests that are waiting: per corpus it merges their patterns (identical
+ * patterns are searched once), and a step scans all its corpora in one
+ * persistent launch (the batch path of rk.h).  Each step runs count ->
+ * admission -> collect: the count pass gives the exact output size, the step
+ * is admitted when that much of the output arena is free, then collect writes
+ * every hit into its slice and the server splits the results per request.
+ * Several steps are in flight at once on separate streams, so requests that
+ * arrive while others run on the device are admitted as slots and arena space
+ * free up.  Launches of a step are replayed from HIP graphs captured once per
+ * stream slot, with the kernel parameters of each step set on the graph.
+ *
+ * Results are exact and identical to a solo rk_count/rk_collect of the same
+ * request: merging only changes which patterns share a scan.
+ */
+#ifndef RK_SERVER_H
+#define RK_SERVER_H
+
+#include "rk.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rk_server rk_server;
+
+typedef struct {
+  uint64_t arena_bytes;        /* device memory for hits of steps in flight (default 1 GiB) */
+  uint32_t max_inflight;       /* steps in flight on the device, 1..8 (default 2) */
+  uint32_t max_step_requests;  /* requests merged into one step (default 4096) */
+  uint32_t max_step_patterns;  /* merged patterns per step (default 262144) */
+  int mode;                    /* rk_mode of every search */
+  int use_graphs;              /* 1: replay captured HIP graphs; 0: plain launches */
+} rk_server_cfg;
+
+/* Fills cfg with the defaults above. */
+void rk_server_cfg_default(rk_server_cfg *cfg);
+
+typedef struct {
+  rk_status status;            /* RK_OK done, RK_EBUSY pending, RK_ECANCELED, or the step's error */
+  uint32_t k;                  /* patterns of the request */
+  const uint64_t *offsets;     /* host, k+1 entries; valid until rk_server_release */
+  const uint64_t *positions;   /* host, offsets[k] entries, per pattern ascending */
+  double t_submit, t_start, t_done; /* seconds on the server's monotonic clock */
+  uint64_t step;               /* step that served the request */
+} rk_result_view;
+
+typedef struct {
+  uint64_t submitted, completed, canceled, failed;
+  uint64_t steps;
+  uint64_t bytes_scanned;      /* corpus bytes scanned by all steps */
+  uint64_t merged_patterns;    /* patterns searched after merging, over all steps */
+  uint64_t request_patterns;   /* patterns submitted, over all completed requests */
+  double p50_ms, p99_ms, mean_ms, max_ms; /* submit -> done latency of completed requests */
+  double busy_s;               /* wall time with at least one step in flight */
+  uint64_t arena_high_water;   /* bytes */
+  uint32_t queue_depth;        /* requests waiting for a step */
+  uint32_t inflight;           /* steps on the device */
+  uint64_t admission_waits;    /* counted steps that waited for arena space */
+} rk_server_stats;
+
+/* Creates a server on ctx's device.  The server owns its streams, graphs,
+ * arena and scheduler thread; ctx must outlive it and is not used by the
+ * server's thread (the server keeps its own context on the same device). */
+rk_status rk_server_create(rk_ctx *ctx, const rk_server_cfg *cfg, rk_server **out);
+/* Registers a resident corpus (device memory, 16-byte aligned, caller-owned,
+ * unchanged while the server runs).  Thread-safe. */
+rk_status rk_server_add_corpus(rk_server *srv, const uint8_t *text_dev, uint64_t n, uint32_t *corpus_id);
+/* Queues a search of corpus_id for k patterns (host arrays, copied).
+ * Thread-safe.  Pattern lengths as in rk.h. */
+rk_status rk_server_submit(rk_server *srv, uint32_t corpus_id, const uint8_t *bytes_host,
+                           const uint64_t *offsets_host, uint32_t k, uint64_t *req_id);
+/* Non-blocking: RK_EBUSY while the request is pending, else fills out. */
+rk_status rk_server_poll(rk_server *srv, uint64_t req_id, rk_result_view *out);
+/* Blocks until the request is done or timeout_s passes (RK_EBUSY). */
+rk_status rk_server_wait(rk_server *srv, uint64_t req_id, double timeout_s, rk_result_view *out);
+/* Cancels a request that has not been put into a step (RK_EBUSY otherwise). */
+rk_status rk_server_cancel(rk_server *srv, uint64_t req_id);
+/* Frees a finished request's results. */
+rk_status rk_server_release(rk_server *srv, uint64_t req_id);
+/* Blocks until every submitted request is finished. */
+rk_status rk_server_drain(rk_server *srv);
+rk_status rk_server_get_stats(rk_server *srv, rk_server_stats *out);
+/* Clears the latency record and counters (corpora and requests stay). */
+rk_status rk_server_reset_stats(rk_server *srv);
+/* Stops the scheduler (pending requests end RK_ECANCELED) and frees everything. */
+void rk_server_destroy(rk_server *srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RK_SERVER_H */

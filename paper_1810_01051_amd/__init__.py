@@ -10,5 +10,6 @@ from ._lib import load as _load
 _load()
 
 from .search import (BatchPlan, Context, Plan, default_context, search, split)  # noqa: E402,F401
+from .server import Server  # noqa: E402,F401
 
-__all__ = ["Context", "Plan", "BatchPlan", "search", "split", "default_context"]
+__all__ = ["Context", "Plan", "BatchPlan", "Server", "search", "split", "default_context"]

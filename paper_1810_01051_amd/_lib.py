@@ -2,7 +2,7 @@
 
 Argument marshalling only: every step of the search runs inside librk.  The
 library is loaded from this package directory; if it is missing the import
-fails loudly (build it with ``python -m paper_1810_01051_amd.build``).
+fails loudly (build it with ``python paper_1810_01051_amd/build.py``).
 """
 from __future__ import annotations
 
@@ -10,7 +10,8 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "librk.so")
+# RK_LIBRARY may name another build of librk (for A/B runs of build variants)
+LIB_PATH = os.environ.get("RK_LIBRARY") or os.path.join(HERE, "librk.so")
 
 RK_OK = 0
 RK_EINVAL = -1
@@ -46,8 +47,42 @@ class RkInstance(ctypes.Structure):
                 ("offsets_host", c_void), ("k", ctypes.c_uint32)]
 
 
-# name -> (restype, argtypes); the list mirrors include/rk.h
+class RkServerCfg(ctypes.Structure):
+    _fields_ = [("arena_bytes", ctypes.c_uint64), ("max_inflight", ctypes.c_uint32),
+                ("max_step_requests", ctypes.c_uint32), ("max_step_patterns", ctypes.c_uint32),
+                ("mode", ctypes.c_int), ("use_graphs", ctypes.c_int)]
+
+
+class RkResultView(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("k", ctypes.c_uint32), ("offsets", c_u64p), ("positions", c_u64p),
+                ("t_submit", ctypes.c_double), ("t_start", ctypes.c_double), ("t_done", ctypes.c_double),
+                ("step", ctypes.c_uint64)]
+
+
+class RkServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("canceled", ctypes.c_uint64),
+                ("failed", ctypes.c_uint64), ("steps", ctypes.c_uint64), ("bytes_scanned", ctypes.c_uint64),
+                ("merged_patterns", ctypes.c_uint64), ("request_patterns", ctypes.c_uint64),
+                ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
+                ("max_ms", ctypes.c_double), ("busy_s", ctypes.c_double), ("arena_high_water", ctypes.c_uint64),
+                ("queue_depth", ctypes.c_uint32), ("inflight", ctypes.c_uint32),
+                ("admission_waits", ctypes.c_uint64)]
+
+
+# name -> (restype, argtypes); the list mirrors include/rk.h and include/rk_server.h
 SIGNATURES = {
+    "rk_server_cfg_default": (None, [ctypes.POINTER(RkServerCfg)]),
+    "rk_server_create": (ctypes.c_int, [c_void, ctypes.POINTER(RkServerCfg), ctypes.POINTER(c_void)]),
+    "rk_server_add_corpus": (ctypes.c_int, [c_void, c_void, ctypes.c_uint64, c_u32p]),
+    "rk_server_submit": (ctypes.c_int, [c_void, ctypes.c_uint32, c_void, c_void, ctypes.c_uint32, c_u64p]),
+    "rk_server_poll": (ctypes.c_int, [c_void, ctypes.c_uint64, ctypes.POINTER(RkResultView)]),
+    "rk_server_wait": (ctypes.c_int, [c_void, ctypes.c_uint64, ctypes.c_double, ctypes.POINTER(RkResultView)]),
+    "rk_server_cancel": (ctypes.c_int, [c_void, ctypes.c_uint64]),
+    "rk_server_release": (ctypes.c_int, [c_void, ctypes.c_uint64]),
+    "rk_server_drain": (ctypes.c_int, [c_void]),
+    "rk_server_get_stats": (ctypes.c_int, [c_void, ctypes.POINTER(RkServerStats)]),
+    "rk_server_reset_stats": (ctypes.c_int, [c_void]),
+    "rk_server_destroy": (None, [c_void]),
     "rk_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "rk_ctx_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64, ctypes.POINTER(c_void)]),
     "rk_ctx_destroy": (None, [c_void]),
@@ -75,6 +110,7 @@ SIGNATURES = {
     "rk_batch_plan_create": (ctypes.c_int, [c_void, ctypes.POINTER(RkInstance), ctypes.c_uint32, ctypes.c_int,
                                             ctypes.POINTER(c_void)]),
     "rk_plan_text_bytes": (ctypes.c_uint64, [c_void]),
+    "rk_stream_read": (ctypes.c_int, [c_void, c_void, ctypes.c_uint64, c_void, ctypes.c_uint32, c_void]),
     "rk_autotune": (ctypes.c_int, [c_void, ctypes.c_uint64, c_u32p, ctypes.c_uint32, ctypes.c_char_p]),
     "rk_autotune_load": (ctypes.c_int, [c_void, ctypes.c_char_p]),
     "rk_autotune_choice": (ctypes.c_int, [c_void, ctypes.c_int, ctypes.c_uint32]),
@@ -89,7 +125,7 @@ def load() -> ctypes.CDLL:
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
-        raise ImportError("librk.so not found at %s; build it with `python -m paper_1810_01051_amd.build` "
+        raise ImportError("librk.so not found at %s; build it with `python paper_1810_01051_amd/build.py` "
                           "(the HIP path has no fallback)" % LIB_PATH)
     lib = ctypes.CDLL(LIB_PATH)
     for name, (res, args) in SIGNATURES.items():

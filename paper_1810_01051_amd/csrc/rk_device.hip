@@ -31,6 +31,22 @@
 
 #include "rk_internal.h"
 
+// Build-time variants of the scan (the defaults are the measured best on gfx950):
+//   RK_PREFETCH  1: a workgroup issues the next tile's loads before processing
+//                   the current one; 0: loads, then waits, per tile.
+//   RK_MIN_ACC   1: single-target screen ORs matches through a VGPR minimum;
+//                0: through per-window wave ballots.
+//   RK_WAVES     >0: minimum waves per SIMD requested from the compiler.
+#ifndef RK_PREFETCH
+#define RK_PREFETCH 1
+#endif
+#ifndef RK_MIN_ACC
+#define RK_MIN_ACC 0
+#endif
+#ifndef RK_WAVES
+#define RK_WAVES 0
+#endif
+
 namespace rk {
 
 // ------------------------------------------------------------ arithmetic mod q
@@ -125,7 +141,7 @@ __device__ __forceinline__ void pass_list_screen(const uint32_t *tw, uint32_t ms
   uint32_t h = 0, acc = 0;
 #pragma unroll
   for (int j = 64 - WU; j < 64; ++j) h = (h << S) + byte_at(w, j);
-  if (ANY && NT == 1) {
+  if (RK_MIN_ACC && ANY && NT == 1) {
     // one target: the minimum of h ^ target over the windows is zero iff
     // some window matches; no per-window scalar work
     uint32_t mn = 0xFFFFFFFFu;
@@ -349,16 +365,25 @@ __device__ __forceinline__ uint64_t horner_exact(const uint8_t *p, uint32_t m) {
   return canon(s);
 }
 
-// Head of the chain of local pattern indices whose exact hash is H, or kNoLink.
-__device__ __forceinline__ uint32_t exact_lookup(const uint8_t *img, const BucketDesc &D, uint64_t H) {
-  const uint64_t *keys = (const uint64_t *)(img + D.ex_off);
-  const uint32_t *heads = (const uint32_t *)(img + D.ex_off + 8u * (D.ex_mask + 1u));
-  uint32_t slot = (uint32_t)H & D.ex_mask;
-  for (uint32_t probe = 0; probe <= D.ex_mask; ++probe) {
+// Shift-add hash of the span = 32/s bytes ending at *end (the value the scan's
+// screen pass held for that window end), masked as the group's hash is.
+__device__ __forceinline__ uint32_t screen_key(const uint8_t *end, uint32_t shift, uint32_t mask) {
+  const uint32_t span = 32u / shift;
+  uint32_t h = 0;
+  for (uint32_t j = span; j-- > 0;) h = (h << shift) + end[-(int)j];
+  return h & mask;
+}
+
+// Run of entries (first | count << 16) stored under key, or kNoLink.
+__device__ __forceinline__ uint32_t key_lookup(const uint8_t *img, const BucketDesc &D, uint64_t key) {
+  const uint64_t *keys = (const uint64_t *)(img + D.ht_off);
+  const uint32_t *runs = (const uint32_t *)(img + D.ht_off + 8u * (D.ht_mask + 1u));
+  uint32_t slot = ht_slot(key, D.ht_mask);
+  for (uint32_t probe = 0; probe <= D.ht_mask; ++probe) {
     const uint64_t k = keys[slot];
-    if (k == H) return heads[slot];
+    if (k == key) return runs[slot];
     if (k == kEmptyKey) return kNoLink;
-    slot = (slot + 1u) & D.ex_mask;
+    slot = (slot + 1u) & D.ht_mask;
   }
   return kNoLink;
 }
@@ -369,11 +394,43 @@ __device__ __forceinline__ bool bytes_equal(const uint8_t *a, const uint8_t *b, 
   return true;
 }
 
+// Walks the run of entries found for the candidate window ending at *end
+// (global end index e) and calls hit(entry) for every pattern that occurs
+// there: the window of the entry's length must start inside the text, have
+// the entry's exact hash and equal bytes.  Entries of a run are sorted by
+// length, so one backward pass accumulates the exact hash of every suffix:
+// S_m = sum_{j<m} T[e-j] * 256^j = hash of the m-byte window ending at e.
+template <typename F>
+__device__ __forceinline__ void verify_run(const uint8_t *img, const BucketDesc &D, uint32_t run, const uint8_t *end,
+                                           int64_t e, F &&hit) {
+  if (run == kNoLink) return;
+  const Entry *ent = (const Entry *)(img + D.ent_off);
+  const uint32_t first = run & 0xFFFFu, cnt = run >> 16;
+  uint64_t S = 0;   // lazy: < 2^62
+  uint32_t j = 0;   // bytes accumulated
+  uint32_t r = 0;   // 8j mod 61
+  for (uint32_t t = first; t < first + cnt; ++t) {
+    const uint32_t m = ent[t].off_m >> 24;
+    if (e - (int64_t)m + 1 < 0) continue;  // window would start before the text
+    for (; j < m; ++j) {
+      S += rot61((uint64_t)end[-(int)j], r);
+      S = (S & kQ) + (S >> 61);
+      r = (r + 8u >= 61u) ? r + 8u - 61u : r + 8u;
+    }
+    if (canon(S) != ent[t].hx) continue;
+    if (bytes_equal(end - (m - 1), img + D.pat_off + (ent[t].off_m & 0xFFFFFFu), m)) hit(ent[t]);
+  }
+}
+
 // ------------------------------------------------------------ the scan kernel
 //
 // LDS: [tile: kFront + W + 16][cand: kCandCap u32][misc: 64 u32][image: img_cap]
 template <int WG, int C, int FAM>
-__global__ __launch_bounds__(WG, 4) void scan_kernel(ScanParams p) {
+#if RK_WAVES > 0
+__global__ __launch_bounds__(WG, RK_WAVES) void scan_kernel(ScanParams p) {
+#else
+__global__ __launch_bounds__(WG) void scan_kernel(ScanParams p) {
+#endif
   constexpr uint32_t W = WG * C;
   constexpr uint32_t TILE_LDS = (kFront + W + 16 + 15) & ~15u;
   constexpr uint32_t NCH = (kFront + W) / 16;  // 16-byte chunks loaded per tile
@@ -442,10 +499,11 @@ __global__ __launch_bounds__(WG, 4) void scan_kernel(ScanParams p) {
   Item cur;
   if (item < nitems) {
     cur = locate(item);
-    issue_loads(cur);
+    if (RK_PREFETCH) issue_loads(cur);
   }
   while (item < nitems) {
     const uint64_t next = pop();  // ends with a barrier when a queue is used
+    if (!RK_PREFETCH) issue_loads(cur);
     __syncthreads();  // previous tile finished with tile / cand / image
     if (cur.inst != cur_inst) {
       const uint4 *src = (const uint4 *)(p.blob + p.inst[cur.inst].img_off);
@@ -464,7 +522,7 @@ __global__ __launch_bounds__(WG, 4) void scan_kernel(ScanParams p) {
     Item nx;
     if (next < nitems) {
       nx = locate(next);
-      issue_loads(nx);
+      if (RK_PREFETCH) issue_loads(nx);
     }
     const uint64_t gt = cur.gt;
     const uint64_t n = cur.n;
@@ -493,10 +551,10 @@ __global__ __launch_bounds__(WG, 4) void scan_kernel(ScanParams p) {
       for (int j = 0; j < 4; ++j) D.tgt[j] = uni(dp->tgt[j]);
       D.fp_off = uni(dp->fp_off);
       D.fp_mask = uni(dp->fp_mask);
-      D.ex_off = uni(dp->ex_off);
-      D.ex_mask = uni(dp->ex_mask);
-      D.link_off = uni(dp->link_off);
-      D.pid_off = uni(dp->pid_off);
+      D.ht_off = uni(dp->ht_off);
+      D.ht_mask = uni(dp->ht_mask);
+      D.ent_off = uni(dp->ent_off);
+      D.max_m = uni(dp->max_m);
       D.pat_off = uni(dp->pat_off);
       D.npat = uni(dp->npat);
       const uint32_t m = D.m;
@@ -575,30 +633,28 @@ __global__ __launch_bounds__(WG, 4) void scan_kernel(ScanParams p) {
         const uint32_t nc = min(kCandCap, ncand - r0);
         for (uint32_t i0 = 0; i0 < nc; i0 += WG) {
           const uint32_t ci = i0 + tid;
-          uint32_t e_rel = 0, head = kNoLink, nh = 0;
-          const uint8_t *win = nullptr;
+          uint32_t run = kNoLink, nh = 0;
+          const uint8_t *end = nullptr;
+          int64_t e = 0;
+          const bool screen = D.kind == kListScreen || D.kind == kTableScreen;
           if (ci < nc) {
-            e_rel = cand[ci];
-            win = tile + kFront + e_rel + 1 - m;
-            const uint64_t Hx = horner_exact(win, m);
-            head = exact_lookup(img, D, Hx);
-            const uint32_t *link = (const uint32_t *)(img + D.link_off);
-            for (uint32_t li = head; li != kNoLink; li = link[li])
-              nh += bytes_equal(win, img + D.pat_off + li * m, m);
+            const uint32_t e_rel = cand[ci];
+            end = tile + kFront + e_rel;
+            e = tstart + (int64_t)e_rel;
+            const uint64_t key = screen ? (uint64_t)screen_key(end, D.shift & 0xFFu, D.mask)
+                                        : horner_exact(end - (m - 1), m);
+            run = key_lookup(img, D, key);
+            verify_run(img, D, run, end, e, [&](const Entry &) { ++nh; });
           }
           uint32_t nht;
           const uint32_t hb = block_excl_scan<WG>(nh, misc, nht);
           if (nh) {
-            const uint32_t *link = (const uint32_t *)(img + D.link_off);
-            const uint32_t *pid = (const uint32_t *)(img + D.pid_off);
-            const uint64_t x = (uint64_t)(tstart + (int64_t)e_rel + 1 - (int64_t)m);
             uint32_t o = tile_hits + hb;
-            for (uint32_t li = head; li != kNoLink; li = link[li]) {
-              if (bytes_equal(win, img + D.pat_off + li * m, m)) {
-                if (o < cap) slab[o] = ((uint64_t)pid[li] << kPosBits) | x;
-                ++o;
-              }
-            }
+            verify_run(img, D, run, end, e, [&](const Entry &en) {
+              const uint64_t x = (uint64_t)(e - (int64_t)(en.off_m >> 24) + 1);
+              if (o < cap) slab[o] = ((uint64_t)en.pid << kPosBits) | x;
+              ++o;
+            });
           }
           tile_hits += nht;
         }
@@ -826,13 +882,7 @@ __global__ void window_hashes_kernel(const uint8_t *text, uint64_t n, uint32_t m
 // ------------------------------------------------------------------ launchers
 template <int WG, int C, int FAM>
 static hipError_t launch_scan_t(const ScanParams &p, uint32_t grid, uint32_t lds_bytes, hipStream_t s) {
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void *)scan_kernel<WG, C, FAM>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
+  // the dynamic LDS limit was raised by prepare_scan_kernels() at context creation
   hipLaunchKernelGGL((scan_kernel<WG, C, FAM>), dim3(grid), dim3(WG), lds_bytes, s, p);
   return hipGetLastError();
 }
@@ -965,6 +1015,58 @@ hipError_t launch_window_hashes(const uint8_t *text, uint64_t n, uint32_t m, con
   if (cnt == 0) return hipSuccess;
   hipLaunchKernelGGL(window_hashes_kernel, dim3((uint32_t)((cnt + 255) / 256)), dim3(256), 0, s, text, n, m, xs, cnt,
                      out);
+  return hipGetLastError();
+}
+
+// Raises the dynamic LDS limit of every scan kernel once, outside any stream
+// capture (a graph capture must not run first-time setup calls).
+template <int FAM>
+static void prepare_fam() {
+  (void)hipFuncSetAttribute((const void *)scan_kernel<256, 68, FAM>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            160 * 1024);
+  (void)hipFuncSetAttribute((const void *)scan_kernel<256, 132, FAM>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            160 * 1024);
+  (void)hipFuncSetAttribute((const void *)scan_kernel<512, 68, FAM>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            160 * 1024);
+  (void)hipFuncSetAttribute((const void *)scan_kernel<256, 36, FAM>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            160 * 1024);
+}
+
+void prepare_scan_kernels() {
+  prepare_fam<kFamScreen1>();
+  prepare_fam<kFamScreen>();
+  prepare_fam<kFamExact>();
+}
+
+}  // namespace rk
+
+namespace rk {
+
+// ----------------------------------------------------- stream-read roofline
+// Reads every 16-byte block of data[0..n) once (the scan's load width, fully
+// coalesced, grid-stride) and folds it into one word per workgroup so that
+// nothing is optimised away: the read-bandwidth ceiling the scan is held to.
+__global__ __launch_bounds__(256) void stream_read_kernel(const uint4 *data, uint64_t nblk, uint32_t *out) {
+  uint32_t acc = 0;
+  const uint64_t stride = (uint64_t)gridDim.x * 256u;
+  uint64_t i = (uint64_t)blockIdx.x * 256u + threadIdx.x;
+  for (; i + 3 * stride < nblk; i += 4 * stride) {
+    const uint4 a = data[i], b = data[i + stride], c = data[i + 2 * stride], d = data[i + 3 * stride];
+    acc ^= a.x ^ a.y ^ a.z ^ a.w ^ b.x ^ b.y ^ b.z ^ b.w ^ c.x ^ c.y ^ c.z ^ c.w ^ d.x ^ d.y ^ d.z ^ d.w;
+  }
+  for (; i < nblk; i += stride) {
+    const uint4 a = data[i];
+    acc ^= a.x ^ a.y ^ a.z ^ a.w;
+  }
+  for (int d = 32; d >= 1; d >>= 1) acc ^= __shfl_xor(acc, d, 64);
+  __shared__ uint32_t red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) out[blockIdx.x] = red[0] ^ red[1] ^ red[2] ^ red[3];
+}
+
+hipError_t launch_stream_read(const void *data, uint64_t n, uint32_t *out, uint32_t grid, hipStream_t s) {
+  hipLaunchKernelGGL(stream_read_kernel, dim3(grid), dim3(256), 0, s, (const uint4 *)data, n / 16, out);
   return hipGetLastError();
 }
 

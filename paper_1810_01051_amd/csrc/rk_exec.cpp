@@ -15,7 +15,6 @@
 namespace rk {
 
 // images are built per real instance (defined in rk_host.cpp)
-struct BucketIn;
 rk_status build_instance_images(rk_ctx *ctx, const uint8_t *bytes, const uint64_t *offs, uint32_t k,
                                 uint32_t pid_base, int mode, uint32_t src, std::vector<VInst> &vinsts,
                                 std::vector<uint8_t> &blob);
@@ -29,39 +28,30 @@ static int pick_cfg(const rk_ctx *ctx, int mode, uint32_t m) {
   return 0;
 }
 
-rk_status plan_build(rk_ctx *ctx, const rk_instance *inst, uint32_t count, int mode, bool batch, rk_plan **out) {
+// Host half of a plan: images, and for batches the instance descriptors and
+// the work-queue order.  P receives everything but device memory; the three
+// byte arrays are what plan_upload copies to the device.
+rk_status plan_build_host(rk_ctx *ctx, const rk_instance *inst, uint32_t count, int mode, bool batch, rk_plan *P,
+                          std::vector<uint8_t> &blob, std::vector<InstDesc> &descs, std::vector<uint64_t> &items) {
   if (mode == RK_MODE_AUTO) mode = RK_MODE_SCREEN;
   if (mode != RK_MODE_EXACT && mode != RK_MODE_SCREEN) return set_err(ctx, RK_EINVAL, "unknown mode %d", mode);
-  if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, RK_EDEVICE, "hipSetDevice failed");
-  rk_plan *P = new (std::nothrow) rk_plan();
-  if (!P) return set_err(ctx, RK_ENOMEM, "plan allocation");
   P->device = ctx->device;
   P->mode = mode;
   P->batch = batch;
-  std::vector<uint8_t> blob;
+  blob.clear();
+  descs.clear();
+  items.clear();
   uint64_t ktot = 0;
   // weight of each length (bytes x patterns) to pick one scan geometry
   std::map<uint32_t, double> mweight;
   for (uint32_t i = 0; i < count; ++i) {
     const rk_instance &I = inst[i];
     if (batch) {
-      if (I.n && !I.text_dev) {
-        delete P;
-        return set_err(ctx, RK_EINVAL, "instance %u: null text", i);
-      }
-      if (((uintptr_t)I.text_dev & 15u) != 0) {
-        delete P;
-        return set_err(ctx, RK_EINVAL, "instance %u: text not 16-byte aligned", i);
-      }
-      if (I.n > RK_MAX_N) {
-        delete P;
-        return set_err(ctx, RK_EUNSUPPORTED, "instance %u: text too long", i);
-      }
+      if (I.n && !I.text_dev) return set_err(ctx, RK_EINVAL, "instance %u: null text", i);
+      if (((uintptr_t)I.text_dev & 15u) != 0) return set_err(ctx, RK_EINVAL, "instance %u: text not 16-byte aligned", i);
+      if (I.n > RK_MAX_N) return set_err(ctx, RK_EUNSUPPORTED, "instance %u: text too long", i);
     }
-    if (ktot + I.k > RK_MAX_PID) {
-      delete P;
-      return set_err(ctx, RK_EUNSUPPORTED, "more than %u patterns in one plan", RK_MAX_PID);
-    }
+    if (ktot + I.k > RK_MAX_PID) return set_err(ctx, RK_EUNSUPPORTED, "more than %u patterns in one plan", RK_MAX_PID);
     RealInst R;
     R.text = I.text_dev;
     R.n = I.n;
@@ -70,10 +60,7 @@ rk_status plan_build(rk_ctx *ctx, const rk_instance *inst, uint32_t count, int m
     P->insts.push_back(R);
     rk_status st = build_instance_images(ctx, I.bytes_host, I.offsets_host, I.k, (uint32_t)ktot, mode, i,
                                          P->vinsts, blob);
-    if (st != RK_OK) {
-      delete P;
-      return st;
-    }
+    if (st != RK_OK) return st;
     for (uint32_t j = 0; j < I.k; ++j) {
       const uint32_t m = (uint32_t)(I.offsets_host[j + 1] - I.offsets_host[j]);
       mweight[m] += (double)(batch ? I.n : 1) + 1.0;
@@ -95,10 +82,6 @@ rk_status plan_build(rk_ctx *ctx, const rk_instance *inst, uint32_t count, int m
     if (mode != RK_MODE_EXACT && !v.only_one_list) P->fam = kFamScreen;
   for (const VInst &v : P->vinsts) P->img_cap = std::max(P->img_cap, v.img_bytes);
   P->img_cap = (uint32_t)align_up(P->img_cap, 16);
-
-  // batch: fixed instance descriptors and the work-queue order
-  std::vector<InstDesc> descs;
-  std::vector<uint64_t> items;
   if (batch) {
     const uint32_t W = kTileCfgs[P->cfg].wg * kTileCfgs[P->cfg].c;
     uint64_t base = 0;
@@ -116,7 +99,7 @@ rk_status plan_build(rk_ctx *ctx, const rk_instance *inst, uint32_t count, int m
       base += d.ntiles;
     }
     P->total_tiles = base;
-    // queue order: heavier tiles (more buckets, longer patterns) first, then by
+    // queue order: heavier tiles (more groups, longer patterns) first, then by
     // instance, so a workgroup keeps one instance image across consecutive pops
     std::vector<uint32_t> order(P->vinsts.size());
     for (uint32_t i = 0; i < order.size(); ++i) order[i] = i;
@@ -129,9 +112,31 @@ rk_status plan_build(rk_ctx *ctx, const rk_instance *inst, uint32_t count, int m
       for (uint64_t t = 0; t < descs[vi].ntiles; ++t) items.push_back(descs[vi].tile_base + t);
     P->nitems = items.size();
   }
-  const uint64_t blob_bytes = align_up(std::max<size_t>(blob.size(), 16), 256);
-  const uint64_t desc_bytes = align_up(descs.size() * sizeof(InstDesc), 256);
-  const uint64_t item_bytes = align_up(items.size() * 8, 256);
+  return RK_OK;
+}
+
+// Device layout of a plan's three arrays inside one allocation.
+void plan_sizes(const std::vector<uint8_t> &blob, const std::vector<InstDesc> &descs, const std::vector<uint64_t> &items,
+                uint64_t *blob_bytes, uint64_t *desc_bytes, uint64_t *item_bytes) {
+  *blob_bytes = align_up(std::max<size_t>(blob.size(), 16), 256);
+  *desc_bytes = align_up(descs.size() * sizeof(InstDesc), 256);
+  *item_bytes = align_up(items.size() * 8, 256);
+}
+
+rk_status plan_build(rk_ctx *ctx, const rk_instance *inst, uint32_t count, int mode, bool batch, rk_plan **out) {
+  if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, RK_EDEVICE, "hipSetDevice failed");
+  rk_plan *P = new (std::nothrow) rk_plan();
+  if (!P) return set_err(ctx, RK_ENOMEM, "plan allocation");
+  std::vector<uint8_t> blob;
+  std::vector<InstDesc> descs;
+  std::vector<uint64_t> items;
+  rk_status st = plan_build_host(ctx, inst, count, mode, batch, P, blob, descs, items);
+  if (st != RK_OK) {
+    delete P;
+    return st;
+  }
+  uint64_t blob_bytes, desc_bytes, item_bytes;
+  plan_sizes(blob, descs, items, &blob_bytes, &desc_bytes, &item_bytes);
   const uint64_t all = blob_bytes + desc_bytes + item_bytes;
   if (hipMalloc(&P->dev, all) != hipSuccess) {
     delete P;
@@ -147,10 +152,10 @@ rk_status plan_build(rk_ctx *ctx, const rk_instance *inst, uint32_t count, int m
   if (e == hipSuccess && !items.empty())
     e = hipMemcpy(P->items_dev, items.data(), items.size() * 8, hipMemcpyHostToDevice);
   if (e != hipSuccess) {
-    rk_status st = hip_err(ctx, e, "plan upload");
+    rk_status st2 = hip_err(ctx, e, "plan upload");
     hipFree(P->dev);
     delete P;
-    return st;
+    return st2;
   }
   *out = P;
   return RK_OK;
@@ -373,13 +378,26 @@ rk_status collect_enqueue(rk_ctx *ctx, const rk_plan *plan, const uint8_t *text,
       total = mm.total;
       overflow = mm.overflow;
     }
-  hipError_t e;
   if (total == ~0ull) {
-    e = hipMemcpyAsync(ctx->pinned, sc + L.ctr, 8, hipMemcpyDeviceToHost, s);
+    hipError_t e = hipMemcpyAsync(ctx->pinned, sc + L.ctr, 8, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_err(ctx, e, "total readback");
     total = ctx->pinned[0];
   }
+  return collect_enqueue_known(ctx, plan, n, scratch, scratch_bytes, work, work_bytes, offsets, positions, capacity,
+                               total, overflow, s);
+}
+
+// Collect with the count pass's total and overflowed-tile count given by the
+// caller (overflow = all ones: unknown, the rescan is launched).
+rk_status collect_enqueue_known(rk_ctx *ctx, const rk_plan *plan, uint64_t n, void *scratch, uint64_t scratch_bytes,
+                                void *work, uint64_t work_bytes, uint64_t *offsets, uint64_t *positions,
+                                uint64_t capacity, uint64_t total, uint32_t overflow, hipStream_t s) {
+  Layout L;
+  rk_status st = make_layout(ctx, plan, n, L);
+  if (st != RK_OK) return st;
+  uint8_t *sc = (uint8_t *)scratch;
+  hipError_t e;
   if (capacity < total) return set_err(ctx, RK_ENOSPACE, "positions capacity %llu < %llu hits",
                                        (unsigned long long)capacity, (unsigned long long)total);
   if (total && !positions) return set_err(ctx, RK_EINVAL, "null positions");
@@ -523,4 +541,17 @@ extern "C" rk_status rk_scan_dump(rk_ctx *ctx, const uint8_t *text, uint64_t n, 
 extern "C" rk_status rk_autotune(rk_ctx *ctx, uint64_t n, const uint32_t *lengths, uint32_t nlengths,
                                  const char *path) {
   return tune_run(ctx, n, lengths, nlengths, path);
+}
+
+extern "C" rk_status rk_stream_read(rk_ctx *ctx, const void *data, uint64_t n, uint32_t *out, uint32_t grid,
+                                    rk_stream s) {
+  if (!ctx) return RK_EINVAL;
+  if (!data || !out || grid == 0 || (n & 15u) || ((uintptr_t)data & 15u))
+    return set_err(ctx, RK_EINVAL, "stream_read: 16-byte aligned data, n a multiple of 16, grid > 0");
+  if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, RK_EDEVICE, "hipSetDevice failed");
+  int slot = -1;
+  hipError_t e = prof_begin(ctx, (hipStream_t)s, 4, &slot);
+  if (e == hipSuccess) e = launch_stream_read(data, n, out, grid, (hipStream_t)s);
+  if (e == hipSuccess) e = prof_end(ctx, (hipStream_t)s, slot);
+  return e == hipSuccess ? RK_OK : hip_err(ctx, e, "stream_read");
 }

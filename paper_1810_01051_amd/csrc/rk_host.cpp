@@ -80,11 +80,40 @@ static inline uint32_t next_pow2(uint32_t v) {
 }
 
 // ------------------------------------------------------------ image building
-struct BucketIn {
+// An instance image holds, per group of patterns, the structures the scan
+// probes for every window (up to 4 register targets or a fingerprint table)
+// and those it walks for candidates only (a key -> entry-run hash table, the
+// entries and the pattern bytes).
+//
+// Screen mode groups patterns by the part of the window their shift-add hash
+// covers: s=8 hashes the last 4 bytes, s=4 the last 8, s=2 the last 16, and
+// bytes older than that have shifted out of the 32-bit word.  So every pattern
+// of length >= 16 shares one hash stream (its key is the shift-add hash of
+// its last 16 bytes), likewise 8..15 and 4..7; lengths 1..3 get one group each
+// (the hash is masked to the window).  Exact mode needs one rolling stream per
+// length, so it groups by length.
+struct PatRef {
+  uint32_t pid;
+  const uint8_t *p;
   uint32_t m;
-  std::vector<uint32_t> pids;        // global pattern ids (ascending)
-  std::vector<const uint8_t *> pats; // pattern bytes
+  uint64_t key;  // screen hash (screen groups) or exact hash (exact groups)
+  uint64_t hx;   // exact hash
 };
+
+struct GroupIn {
+  bool screen;
+  uint32_t shift, mask;  // screen groups
+  uint32_t m;            // exact groups: the length; screen groups: the shortest length
+  std::vector<PatRef> pats;
+};
+
+static uint32_t screen_mask(uint32_t m) { return (screen_shift(m) == 8 && m < 4) ? (1u << (8 * m)) - 1u : 0xFFFFFFFFu; }
+
+// group id for a pattern length under a mode
+static uint32_t group_id(int mode, uint32_t m) {
+  if (mode == RK_MODE_EXACT || m < 4) return m;
+  return 100 + screen_shift(m);
+}
 
 static bool build_fp_table(const std::vector<uint32_t> &keys, uint32_t bits, std::vector<uint32_t> &tab) {
   const uint32_t S = 1u << bits;
@@ -108,35 +137,25 @@ static bool build_fp_table(const std::vector<uint32_t> &keys, uint32_t bits, std
   return true;
 }
 
-// Appends one bucket's tables to img (16-aligned) and fills its descriptor.
-// Returns false if the bucket's key set does not fit the fingerprint table
-// limit (the caller then splits the bucket).
-static bool emit_bucket(const BucketIn &B, int mode, std::vector<uint8_t> &img, BucketDesc &D) {
-  const uint32_t m = B.m, np = (uint32_t)B.pids.size();
+// Serialises one group into body (offsets relative to the body start) and
+// fills its descriptor.  Returns false if its keys do not fit a fingerprint
+// table of at most 2^13 slots (the caller then splits the group).
+static bool emit_group(const GroupIn &G, int mode, std::vector<uint8_t> &body, BucketDesc &D) {
+  std::vector<PatRef> P = G.pats;
+  std::stable_sort(P.begin(), P.end(), [](const PatRef &a, const PatRef &b) {
+    if (a.key != b.key) return a.key < b.key;
+    if (a.m != b.m) return a.m < b.m;
+    return a.pid < b.pid;
+  });
   memset(&D, 0, sizeof D);
-  D.m = m;
-  D.npat = np;
-  D.mask = 0xFFFFFFFFu;
-  std::vector<uint64_t> hx(np);
-  for (uint32_t i = 0; i < np; ++i) hx[i] = host_hash(B.pats[i], m);
-  // distinct exact hashes -> chains of local indices (ascending)
+  D.m = G.m;
+  D.npat = (uint32_t)P.size();
+  D.mask = G.screen ? G.mask : 0xFFFFFFFFu;
   std::vector<uint64_t> dist;
-  std::vector<uint32_t> link(np, kNoLink);
-  std::map<uint64_t, uint32_t> head, tail;
-  for (uint32_t i = 0; i < np; ++i) {
-    auto it = head.find(hx[i]);
-    if (it == head.end()) {
-      head[hx[i]] = i;
-      tail[hx[i]] = i;
-      dist.push_back(hx[i]);
-    } else {
-      link[tail[hx[i]]] = i;
-      tail[hx[i]] = i;
-    }
-  }
+  for (const PatRef &r : P)
+    if (dist.empty() || dist.back() != r.key) dist.push_back(r.key);
   std::vector<uint32_t> fpkeys;
-  std::vector<uint32_t> fptab;
-  if (mode == RK_MODE_EXACT) {
+  if (!G.screen) {
     std::vector<uint32_t> lazy;
     for (uint64_t H : dist) {
       lazy.push_back((uint32_t)H);
@@ -151,30 +170,27 @@ static bool emit_bucket(const BucketIn &B, int mode, std::vector<uint8_t> &img, 
       for (uint64_t H : dist) fpkeys.push_back((uint32_t)H);
     }
   } else {
-    D.shift = screen_shift(m);
-    if (D.shift == 8 && m < 4) D.mask = (1u << (8 * m)) - 1u;
-    std::vector<uint32_t> sh;
-    for (uint32_t i = 0; i < np; ++i) sh.push_back(screen_hash(B.pats[i], m));
-    std::sort(sh.begin(), sh.end());
-    sh.erase(std::unique(sh.begin(), sh.end()), sh.end());
-    if (sh.size() <= 4) {
+    D.shift = G.shift;
+    if (dist.size() <= 4) {
       D.kind = kListScreen;
-      for (int j = 0; j < 4; ++j) D.tgt[j] = sh[j < (int)sh.size() ? j : 0];
-      D.shift |= (sh.size() == 1 ? 1u : 4u) << 8;  // compare count the kernel unrolls
+      for (int j = 0; j < 4; ++j) D.tgt[j] = (uint32_t)dist[j < (int)dist.size() ? j : 0];
+      D.shift |= (dist.size() == 1 ? 1u : 4u) << 8;  // compare count the kernel unrolls
     } else {
       D.kind = kTableScreen;
-      fpkeys = sh;
+      for (uint64_t h : dist) fpkeys.push_back((uint32_t)h);
     }
   }
-  auto put = [&img](const void *p, size_t bytes) -> uint32_t {
-    const uint32_t off = (uint32_t)align_up(img.size(), 16);
-    img.resize(off + align_up(bytes, 16), 0);
-    memcpy(img.data() + off, p, bytes);
+  auto put = [&body](const void *p, size_t bytes) -> uint32_t {
+    const uint32_t off = (uint32_t)align_up(body.size(), 16);
+    body.resize(off + align_up(bytes, 16), 0);
+    if (bytes) memcpy(body.data() + off, p, bytes);
     return off;
   };
   if (D.kind == kTableScreen || D.kind == kTableExact) {
     uint32_t bits = 6;
-    while ((1u << bits) < 2 * fpkeys.size()) ++bits;
+    while ((1u << bits) < fpkeys.size()) ++bits;
+    ++bits;  // load factor <= 1/2 before the two-way slots
+    std::vector<uint32_t> fptab;
     bool ok = false;
     for (; bits <= 13; ++bits)
       if ((ok = build_fp_table(fpkeys, bits, fptab))) break;
@@ -182,95 +198,98 @@ static bool emit_bucket(const BucketIn &B, int mode, std::vector<uint8_t> &img, 
     D.fp_mask = (1u << bits) - 1;
     D.fp_off = put(fptab.data(), fptab.size() * 4);
   }
-  // exact open-addressing table
-  const uint32_t ES = std::max<uint32_t>(2, next_pow2(2 * (uint32_t)dist.size()));
-  std::vector<uint64_t> keys(ES, kEmptyKey);
-  std::vector<uint32_t> heads(ES, kNoLink);
-  for (uint64_t H : dist) {
-    uint32_t s = (uint32_t)H & (ES - 1);
-    while (keys[s] != kEmptyKey) s = (s + 1) & (ES - 1);
-    keys[s] = H;
-    heads[s] = head[H];
+  // key -> run of entries (first | count << 16), open addressing
+  const uint32_t S = std::max<uint32_t>(2, next_pow2(2 * (uint32_t)dist.size()));
+  std::vector<uint64_t> keys(S, kEmptyKey);
+  std::vector<uint32_t> vals(S, kNoLink);
+  std::vector<Entry> ents(P.size());
+  std::vector<uint8_t> pb;
+  for (size_t i = 0; i < P.size();) {
+    size_t j = i;
+    while (j < P.size() && P[j].key == P[i].key) ++j;
+    uint32_t s = ht_slot(P[i].key, S - 1);
+    while (keys[s] != kEmptyKey) s = (s + 1) & (S - 1);
+    keys[s] = P[i].key;
+    vals[s] = (uint32_t)i | ((uint32_t)(j - i) << 16);
+    i = j;
   }
-  std::vector<uint8_t> ex(ES * 12);
-  memcpy(ex.data(), keys.data(), ES * 8);
-  memcpy(ex.data() + ES * 8, heads.data(), ES * 4);
-  D.ex_mask = ES - 1;
-  D.ex_off = put(ex.data(), ex.size());
-  D.link_off = put(link.data(), np * 4);
-  D.pid_off = put(B.pids.data(), np * 4);
-  std::vector<uint8_t> pb((size_t)np * m);
-  for (uint32_t i = 0; i < np; ++i) memcpy(pb.data() + (size_t)i * m, B.pats[i], m);
+  uint32_t max_m = 0;
+  for (size_t i = 0; i < P.size(); ++i) {
+    ents[i].hx = P[i].hx;
+    ents[i].pid = P[i].pid;
+    ents[i].off_m = (uint32_t)pb.size() | (P[i].m << 24);  // offset relative to the pattern block
+    pb.insert(pb.end(), P[i].p, P[i].p + P[i].m);
+    max_m = std::max(max_m, P[i].m);
+  }
+  std::vector<uint8_t> ht(S * 12);
+  memcpy(ht.data(), keys.data(), S * 8);
+  memcpy(ht.data() + S * 8, vals.data(), S * 4);
+  D.ht_mask = S - 1;
+  D.ht_off = put(ht.data(), ht.size());
+  D.ent_off = put(ents.data(), ents.size() * sizeof(Entry));
   D.pat_off = put(pb.data(), pb.size());
+  D.max_m = max_m;
   return true;
 }
 
-// Splits buckets whose key sets do not fit one fingerprint table.
-static void expand_buckets(const BucketIn &B, int mode, std::vector<std::pair<BucketIn, std::vector<uint8_t>>> &out,
-                           std::vector<BucketDesc> &descs) {
-  std::vector<uint8_t> tmp;
+// Emits G, splitting its pattern list in halves while a fingerprint table
+// cannot hold it.
+static void expand_group(const GroupIn &G, int mode, std::vector<std::vector<uint8_t>> &bodies,
+                         std::vector<BucketDesc> &descs) {
+  std::vector<uint8_t> body;
   BucketDesc D;
-  if (emit_bucket(B, mode, tmp, D) || B.pids.size() < 2) {
-    out.push_back({B, tmp});
+  if (emit_group(G, mode, body, D) || G.pats.size() < 2) {
+    bodies.push_back(body);
     descs.push_back(D);
     return;
   }
-  BucketIn a, b;
-  a.m = b.m = B.m;
-  const size_t h = B.pids.size() / 2;
-  a.pids.assign(B.pids.begin(), B.pids.begin() + h);
-  a.pats.assign(B.pats.begin(), B.pats.begin() + h);
-  b.pids.assign(B.pids.begin() + h, B.pids.end());
-  b.pats.assign(B.pats.begin() + h, B.pats.end());
-  expand_buckets(a, mode, out, descs);
-  expand_buckets(b, mode, out, descs);
+  GroupIn a = G, b = G;
+  const size_t h = G.pats.size() / 2;
+  a.pats.assign(G.pats.begin(), G.pats.begin() + h);
+  b.pats.assign(G.pats.begin() + h, G.pats.end());
+  expand_group(a, mode, bodies, descs);
+  expand_group(b, mode, bodies, descs);
 }
 
-// Builds the images of one real instance: buckets are packed greedily into
-// virtual instances whose image fits kImgLimit bytes.
-static rk_status build_images(rk_ctx *ctx, const std::vector<BucketIn> &buckets, int mode, uint32_t src_inst,
+// Packs groups greedily into virtual instances whose image fits kImgLimit.
+static rk_status build_images(rk_ctx *ctx, const std::vector<GroupIn> &groups, int mode, uint32_t src_inst,
                               std::vector<VInst> &vinsts, std::vector<uint8_t> &blob) {
-  std::vector<std::pair<BucketIn, std::vector<uint8_t>>> parts;
+  std::vector<std::vector<uint8_t>> bodies;
   std::vector<BucketDesc> descs;
-  for (const BucketIn &B : buckets) expand_buckets(B, mode, parts, descs);
-  // a bucket with no table-fitting split (single pattern) always fits
+  for (const GroupIn &G : groups) expand_group(G, mode, bodies, descs);
   size_t i = 0;
-  while (i < parts.size()) {
-    std::vector<uint8_t> img(sizeof(ImageHeader), 0);
-    std::vector<BucketDesc> ds;
-    std::vector<std::vector<uint8_t> *> bodies;
+  while (i < bodies.size()) {
     size_t j = i;
     uint64_t body = 0;
-    uint32_t max_m = 0;
-    while (j < parts.size()) {
-      const uint64_t add = 64 + align_up(parts[j].second.size(), 16);
-      const uint64_t hdr = sizeof(ImageHeader) + 64 * (ds.size() + 1);
+    while (j < bodies.size()) {
+      const uint64_t hdr = sizeof(ImageHeader) + 64 * (j - i + 1);
+      const uint64_t add = align_up(bodies[j].size(), 16);
       if (j > i && hdr + body + add > kImgLimit) break;
-      body += align_up(parts[j].second.size(), 16);
-      ds.push_back(descs[j]);
-      max_m = std::max(max_m, descs[j].m);
+      body += add;
       ++j;
     }
-    const uint32_t hdr = (uint32_t)(sizeof(ImageHeader) + 64 * ds.size());
+    const uint32_t hdr = (uint32_t)(sizeof(ImageHeader) + 64 * (j - i));
     if (hdr + body > kImgLimit)
-      return set_err(ctx, RK_EUNSUPPORTED, "pattern bucket (m=%u) needs %llu bytes of LDS image (limit %u)",
-                     descs[i].m, (unsigned long long)(hdr + body), kImgLimit);
-    img.resize(hdr, 0);
-    for (size_t b = 0; b < ds.size(); ++b) {
+      return set_err(ctx, RK_EUNSUPPORTED, "pattern group needs %llu bytes of LDS image (limit %u)",
+                     (unsigned long long)(hdr + body), kImgLimit);
+    std::vector<uint8_t> img(hdr, 0);
+    uint32_t max_m = 0;
+    bool only_one_list = true;
+    for (size_t b = i; b < j; ++b) {
       const uint32_t base = (uint32_t)img.size();
-      const std::vector<uint8_t> &bb = parts[i + b].second;
-      img.insert(img.end(), bb.begin(), bb.end());
+      img.insert(img.end(), bodies[b].begin(), bodies[b].end());
       img.resize(align_up(img.size(), 16), 0);
-      BucketDesc d = ds[b];
+      BucketDesc d = descs[b];
       if (d.kind == kTableScreen || d.kind == kTableExact) d.fp_off += base;
-      d.ex_off += base;
-      d.link_off += base;
-      d.pid_off += base;
+      d.ht_off += base;
+      d.ent_off += base;
       d.pat_off += base;
-      memcpy(img.data() + sizeof(ImageHeader) + 64 * b, &d, 64);
+      max_m = std::max(max_m, d.max_m);
+      if (d.kind != kListScreen || (d.shift >> 8) != 1u) only_one_list = false;
+      memcpy(img.data() + sizeof(ImageHeader) + 64 * (b - i), &d, 64);
     }
     ImageHeader hd;
-    hd.nbuckets = (uint32_t)ds.size();
+    hd.nbuckets = (uint32_t)(j - i);
     hd.bytes = (uint32_t)align_up(img.size(), 16);
     hd.max_m = max_m;
     hd.pad = 0;
@@ -278,12 +297,11 @@ static rk_status build_images(rk_ctx *ctx, const std::vector<BucketIn> &buckets,
     memcpy(img.data(), &hd, sizeof hd);
     VInst v;
     v.src = src_inst;
-    v.nbuckets = hd.nbuckets;
-    v.max_m = max_m;
-    for (const BucketDesc &d : ds)
-      if (d.kind != kListScreen || (d.shift >> 8) != 1u) v.only_one_list = false;
     v.img_off = (uint32_t)align_up(blob.size(), 256);
     v.img_bytes = hd.bytes;
+    v.nbuckets = hd.nbuckets;
+    v.max_m = max_m;
+    v.only_one_list = only_one_list;
     blob.resize(v.img_off, 0);
     blob.insert(blob.end(), img.begin(), img.end());
     vinsts.push_back(v);
@@ -305,18 +323,31 @@ static rk_status validate_patterns(rk_ctx *ctx, const uint8_t *bytes, const uint
   return RK_OK;
 }
 
-// Buckets (by length) of one instance's patterns with global ids from pid_base.
-static std::vector<BucketIn> bucketize(const uint8_t *bytes, const uint64_t *offs, uint32_t k, uint32_t pid_base) {
-  std::map<uint32_t, BucketIn> by_m;
+// Groups one instance's patterns (global ids from pid_base) for a mode.
+static std::vector<GroupIn> group_patterns(const uint8_t *bytes, const uint64_t *offs, uint32_t k,
+                                           uint32_t pid_base, int mode) {
+  std::map<uint32_t, GroupIn> by;
   for (uint32_t j = 0; j < k; ++j) {
     const uint32_t m = (uint32_t)(offs[j + 1] - offs[j]);
-    BucketIn &B = by_m[m];
-    B.m = m;
-    B.pids.push_back(pid_base + j);
-    B.pats.push_back(bytes + offs[j]);
+    const uint8_t *p = bytes + offs[j];
+    GroupIn &G = by[group_id(mode, m)];
+    PatRef r;
+    r.pid = pid_base + j;
+    r.p = p;
+    r.m = m;
+    r.hx = host_hash(p, m);
+    if (G.pats.empty()) {
+      G.screen = mode != RK_MODE_EXACT;
+      G.shift = screen_shift(m);
+      G.mask = screen_mask(m);
+      G.m = m;
+    }
+    G.m = std::min(G.m, m);
+    r.key = G.screen ? (uint64_t)screen_hash(p, m) : r.hx;
+    G.pats.push_back(r);
   }
-  std::vector<BucketIn> out;
-  for (auto &kv : by_m) out.push_back(kv.second);
+  std::vector<GroupIn> out;
+  for (auto &kv : by) out.push_back(kv.second);
   return out;
 }
 
@@ -326,7 +357,7 @@ rk_status build_instance_images(rk_ctx *ctx, const uint8_t *bytes, const uint64_
   rk_status st = validate_patterns(ctx, bytes, offs, k);
   if (st != RK_OK) return st;
   if (k == 0) return RK_OK;  // nothing to scan for
-  return build_images(ctx, bucketize(bytes, offs, k, pid_base), mode, src, vinsts, blob);
+  return build_images(ctx, group_patterns(bytes, offs, k, pid_base, mode), mode, src, vinsts, blob);
 }
 
 }  // namespace rk
@@ -373,6 +404,7 @@ rk_status rk_ctx_create(int device, uint64_t d, uint64_t q, rk_ctx **out) {
   }
   for (int md = 0; md < 3; ++md)
     for (int m = 0; m <= RK_MAX_M; ++m) c->tune[md][m] = -1;
+  prepare_scan_kernels();
   *out = c;
   return RK_OK;
 }

@@ -27,23 +27,38 @@ enum BucketKind : uint32_t {
   kDump = 4,         // exact rolling state written out for sampled windows (no patterns)
 };
 
-// Bucket descriptor as laid out in an instance image (64 bytes).
+// Group descriptor as laid out in an instance image (64 bytes).  A group is a
+// set of patterns tested with one hash stream: one length in exact mode, one
+// screen-hash span in screen mode.
 struct BucketDesc {
-  uint32_t m;          // pattern length
+  uint32_t m;          // exact groups: the pattern length; screen groups: the shortest length
   uint32_t kind;       // BucketKind
-  uint32_t shift;      // screen shift s in {1,2,4,8} (screen kinds)
+  uint32_t shift;      // screen groups: shift s in bits 0-7, list target count (1 or 4) in bits 8-15
   uint32_t mask;       // screen-hash mask (all ones unless m < 4 with s = 8)
   uint32_t tgt[4];     // list kinds: targets (padded by repetition)
   uint32_t fp_off;     // table kinds: byte offset of the fingerprint table (u32 slots)
   uint32_t fp_mask;    // fingerprint slots - 1
-  uint32_t ex_off;     // byte offset of exact keys (u64[ex_mask+1]), then heads (u32[ex_mask+1])
-  uint32_t ex_mask;    // exact-table slots - 1
-  uint32_t link_off;   // byte offset of u32[npat]: next local index with the same hash
-  uint32_t pid_off;    // byte offset of u32[npat]: global pattern id
-  uint32_t pat_off;    // byte offset of pattern bytes, local pattern i at pat_off + i*m
-  uint32_t npat;       // patterns in this bucket
+  uint32_t ht_off;     // key table: u64 keys[ht_mask+1], then u32 runs[ht_mask+1] (first | count << 16)
+  uint32_t ht_mask;    // key-table slots - 1
+  uint32_t ent_off;    // Entry[npat], sorted by (key, length, pattern id)
+  uint32_t max_m;      // longest pattern in the group
+  uint32_t pat_off;    // pattern bytes; Entry::off_m low 24 bits are relative to this
+  uint32_t npat;       // patterns in this group
 };
 static_assert(sizeof(BucketDesc) == 64, "bucket descriptor is 64 bytes");
+
+// One pattern of a group (16 bytes).
+struct Entry {
+  uint64_t hx;     // exact hash of the pattern, canonical
+  uint32_t pid;    // global pattern id
+  uint32_t off_m;  // byte offset of the pattern (bits 0-23) | length << 24
+};
+static_assert(sizeof(Entry) == 16, "entry is 16 bytes");
+
+// Slot of a key in a group's key table (the host builds it, the kernel probes it).
+__host__ __device__ inline uint32_t ht_slot(uint64_t key, uint32_t mask) {
+  return (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> 40) & mask;
+}
 
 // Header at the start of an instance image (16 bytes), followed by nb descriptors.
 struct ImageHeader {

@@ -194,6 +194,47 @@ def config4(count: int = 4096, lmin: int = 4096, lmax: int = 16 << 20, kmax: int
     return out
 
 
+def config5_corpus(index: int, n: int = 1 << 30, device="cuda:0", chunk_words: int = 1 << 22):
+    """Serving corpus ``index``: the config-3 word text recipe with its own
+    vocabulary and rank stream, drawn on the GPU with torch (seeded Philox) so
+    that 64 corpora of 1 GiB are ready in seconds.  Returns a uint8 tensor."""
+    import torch
+    g = rng(5, 2 * index)
+    lens, letters = zipf_vocab(g)
+    W = len(lens)
+    p = np.arange(1, W + 1, dtype=np.float64) ** (-1.1)
+    cdf = np.cumsum(p)
+    cdf /= cdf[-1]
+    wl = lens + 1
+    wstart = np.zeros(W, dtype=np.int64)
+    wstart[1:] = np.cumsum(wl)[:-1]
+    blob = np.full(int(wl.sum()), ord(" "), dtype=np.uint8)
+    src_off = np.zeros(W, dtype=np.int64)
+    src_off[1:] = np.cumsum(lens)[:-1]
+    blob[np.repeat(wstart - src_off, lens) + np.arange(int(lens.sum()), dtype=np.int64)] = letters
+    dev = torch.device(device)
+    cdf_t = torch.from_numpy(cdf).to(dev)
+    wl_t = torch.from_numpy(wl).to(dev)
+    ws_t = torch.from_numpy(wstart).to(dev)
+    blob_t = torch.from_numpy(blob).to(dev)
+    tg = torch.Generator(device=dev)
+    tg.manual_seed(int(rng(5, 2 * index + 1).integers(0, 2**62)))
+    out = torch.empty(n, dtype=torch.uint8, device=dev)
+    filled = 0
+    while filled < n:
+        u = torch.rand(chunk_words, generator=tg, device=dev, dtype=torch.float64)
+        r = torch.searchsorted(cdf_t, u, right=True).clamp_(max=W - 1)
+        L = wl_t[r]
+        ends = torch.cumsum(L, 0)
+        tot = int(ends[-1])
+        take = min(tot, n - filled)
+        word = torch.repeat_interleave(torch.arange(chunk_words, device=dev), L)[:take]
+        within = torch.arange(take, device=dev) - (ends - L)[word]
+        out[filled:filled + take] = blob_t[ws_t[r[word]] + within]
+        filled += take
+    return out
+
+
 @dataclass
 class Request:
     t_arrival: float

@@ -7,19 +7,21 @@ import re
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "rk.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("rk.h", "rk_server.h")]
 
 
 def declared_functions():
-    src = open(HEADER).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(rk_[a-z0-9_]+)\s*\(", src)))
+    names = set()
+    for h in HEADERS:
+        src = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(rk_[a-z0-9_]+)\s*\(", src))
+    return sorted(names)
 
 
 def test_header_declares_the_boundary():
     names = declared_functions()
     for n in ("rk_ctx_create", "rk_plan_create", "rk_count", "rk_collect", "rk_window_hashes", "rk_scan_dump",
-              "rk_batch_plan_create", "rk_autotune"):
+              "rk_batch_plan_create", "rk_autotune", "rk_server_create", "rk_server_submit", "rk_server_poll"):
         assert n in names
 
 

@@ -1,0 +1,125 @@
+"""Serving: every request's result is the same alone (a solo search through
+the C ABI, and the CPU oracle) and in the mix (merged steps, several steps in
+flight, graph replays, admission waits on a small arena).  Exact equality."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import rkgen
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rk():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1810_01051_amd as rk
+    return rk
+
+
+@pytest.fixture(scope="module")
+def ctx(rk):
+    c = rk.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def corpora():
+    cs = [rkgen.config5_corpus(i, n=(1 << 20) + 64 * i) for i in range(4)]
+    torch.cuda.synchronize()
+    return cs
+
+
+def make_requests(corpora, count, seed, kmax=24):
+    host = [c.cpu().numpy() for c in corpora]
+
+    def sample(ci, g, m):
+        o = int(g.integers(0, len(host[ci]) - m + 1))
+        return host[ci][o:o + m].tobytes()
+
+    reqs = rkgen.config5_requests(rate=1000.0, duration=count / 1000.0, corpora=len(corpora), kmax=kmax,
+                                  sample_text=sample, seed_sub=seed)
+    return reqs, host
+
+
+def solo(ctx, rk, text, pats, mode):
+    plan = rk.Plan(ctx, pats, mode)
+    off, pos = plan.search(text)
+    torch.cuda.synchronize()
+    plan.close()
+    return off.cpu().numpy().astype(np.uint64), pos.cpu().numpy().astype(np.uint64)
+
+
+@pytest.mark.parametrize("mode,graphs,inflight,arena", [
+    ("screen", True, 2, 1 << 28),
+    ("screen", False, 3, 1 << 28),
+    ("exact", True, 2, 1 << 28),
+    ("screen", True, 3, 1 << 26),  # smaller arena: counted steps may wait for memory
+])
+def test_mix_equals_solo_and_oracle(ctx, rk, corpora, mode, graphs, inflight, arena):
+    reqs, host = make_requests(corpora, 48, seed=7)
+    assert len(reqs) > 20
+    srv = rk.Server(ctx, arena_bytes=arena, max_inflight=inflight, max_step_requests=5, mode=mode,
+                    use_graphs=graphs)
+    ids = [srv.add_corpus(c) for c in corpora]
+    assert ids == list(range(len(corpora)))
+    rids = []
+    for r in reqs:
+        rids.append(srv.submit(r.corpus, r.patterns))
+        time.sleep(0.0005)
+    srv.drain()
+    st = srv.stats()
+    assert st["completed"] == len(reqs) and st["failed"] == 0
+    assert st["steps"] >= len(reqs) // 5
+    for i, (r, rid) in enumerate(zip(reqs, rids)):
+        res = srv.wait(rid)
+        assert res["status"] == 0
+        so, sp = solo(ctx, rk, corpora[r.corpus], r.patterns, mode)
+        assert res["offsets"].tolist() == so.tolist(), i
+        assert res["positions"].tolist() == sp.tolist(), i
+        if i % 6 == 0:
+            ro, rp = oracle.search(host[r.corpus], r.patterns, threads=4)
+            assert res["offsets"].tolist() == ro.tolist() and res["positions"].tolist() == rp.tolist(), i
+        srv.release(rid)
+    srv.close()
+
+
+def test_duplicate_patterns_across_requests(ctx, rk, corpora):
+    """Two requests sharing patterns in one step each get their own full lists."""
+    text = corpora[0]
+    h = text.cpu().numpy()
+    a = [h[100:108].tobytes(), h[5000:5016].tobytes(), b"zzzzqqqq"]
+    b = [h[5000:5016].tobytes(), h[100:108].tobytes(), h[100:108].tobytes()]
+    srv = rk.Server(ctx, max_step_requests=8)
+    srv.add_corpus(text)
+    ra, rb = srv.submit(0, a), srv.submit(0, b)
+    srv.drain()
+    xa, xb = srv.wait(ra), srv.wait(rb)
+    assert xa["step"] == xb["step"]
+    oa, pa = oracle.search(h, a)
+    ob, pb = oracle.search(h, b)
+    assert xa["offsets"].tolist() == oa.tolist() and xa["positions"].tolist() == pa.tolist()
+    assert xb["offsets"].tolist() == ob.tolist() and xb["positions"].tolist() == pb.tolist()
+    srv.close()
+
+
+def test_cancel_and_errors(ctx, rk, corpora):
+    srv = rk.Server(ctx, max_inflight=1, max_step_requests=1)
+    srv.add_corpus(corpora[1])
+    rids = [srv.submit(0, [b"abcd", b"e f"]) for _ in range(30)]
+    canceled = sum(1 for r in rids[10:] if srv.cancel(r) == 0)
+    srv.drain()
+    st = srv.stats()
+    assert st["completed"] + st["canceled"] == 30 and st["canceled"] == canceled
+    with pytest.raises(rk._lib.RkError):
+        srv.submit(5, [b"x"])  # unknown corpus
+    with pytest.raises(rk._lib.RkError):
+        srv.submit(0, [b""])
+    empty = srv.wait(srv.submit(0, []))
+    assert empty["status"] == 0 and empty["offsets"].tolist() == [0]
+    srv.close()
