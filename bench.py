@@ -125,6 +125,233 @@ def plan_cfg(ctx, mode):
     return ctx.autotune_choice(m, 32)
 
 
+# ---------------------------------------------------------------- config 4
+def bench_config4(args):
+    """4,096 uneven searches: one persistent launch over all of them (the batch
+    plan's work queue) against one count+collect per instance."""
+    import numpy as np
+    import torch
+    import oracle
+    import rkgen
+    import paper_1810_01051_amd as rk
+    t0 = time.perf_counter()
+    insts = rkgen.config4(count=args.count4)
+    total_bytes = sum(len(s.text) for s in insts)
+    log("config4: %d instances, %d bytes, generated in %.1fs" % (len(insts), total_bytes, time.perf_counter() - t0))
+    offs, o = [], 0
+    for s in insts:
+        offs.append(o)
+        o += (len(s.text) + 255) // 256 * 256
+    buf = torch.empty(o, dtype=torch.uint8, device="cuda:0")
+    for s, off in zip(insts, offs):
+        buf[off:off + len(s.text)].copy_(torch.from_numpy(s.text))
+    texts = [buf[off:off + len(s.text)] for s, off in zip(insts, offs)]
+    torch.cuda.synchronize()
+    ctx = rk.Context(0)
+    if args.tune and os.path.exists(args.tune):
+        ctx.autotune_load(args.tune)
+    res = {}
+    for mode in ("screen", "exact") if not args.no_exact else ("screen",):
+        bp = rk.BatchPlan(ctx, texts, [s.patterns for s in insts], mode)
+        for _ in range(args.warmup):
+            bp.search()
+        torch.cuda.synchronize()
+        lat = []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            t1 = time.perf_counter()
+            off_b, pos_b = bp.search()
+            torch.cuda.synchronize()
+            lat.append(time.perf_counter() - t1)
+        el = time.perf_counter() - t0
+        batched = {"GB/s": round(total_bytes * args.steps / el / 1e9, 2), "ms_per_batch": round(el * 1e3 / args.steps, 3),
+                   "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                   "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3), "hits": int(pos_b.numel())}
+        per = bp.split(off_b, pos_b)
+        # one launch per instance (plans built outside the timed region)
+        plans = [rk.Plan(ctx, s.patterns, mode) for s in insts]
+        scratch = [p.scratch(t.numel(), t.device) for p, t in zip(plans, texts)]
+        for p, t, sc in zip(plans[:8], texts[:8], scratch[:8]):
+            p.collect(t, p.count(t, sc), sc)
+        torch.cuda.synchronize()
+        done = []
+        solo_out = []
+        t0 = time.perf_counter()
+        for p, t, sc in zip(plans, texts, scratch):
+            tot = p.count(t, sc)
+            solo_out.append(p.collect(t, tot, sc))
+            done.append(time.perf_counter() - t0)
+        torch.cuda.synchronize()
+        el1 = time.perf_counter() - t0
+        svc = np.diff([0.0] + done)
+        single = {"GB/s": round(total_bytes / el1 / 1e9, 2), "ms_total": round(el1 * 1e3, 3),
+                  "completion_p50_ms": round(float(np.percentile(done, 50)) * 1e3, 3),
+                  "completion_p99_ms": round(float(np.percentile(done, 99)) * 1e3, 3),
+                  "service_p50_ms": round(float(np.percentile(svc, 50)) * 1e3, 4),
+                  "service_p99_ms": round(float(np.percentile(svc, 99)) * 1e3, 4)}
+        # parity: batched == solo for every instance, oracle on a sample
+        same = True
+        for i, (so, sp) in enumerate(solo_out):
+            lists = rk.split(so, sp)
+            for j in range(len(insts[i].patterns)):
+                if not np.array_equal(per[i][j], lists[j]):
+                    same = False
+        oracle_ok = True
+        for i in range(0, len(insts), max(1, len(insts) // 12)):
+            ro, rp = oracle.search(insts[i].text, insts[i].patterns, threads=8)
+            ref = oracle.split(ro, rp)
+            for j in range(len(insts[i].patterns)):
+                if per[i][j].astype(np.uint64).tolist() != ref[j].tolist():
+                    oracle_ok = False
+        for p in plans:
+            p.close()
+        bp.close()
+        res[mode] = {"batched": batched, "one_launch_per_instance": single, "batch_equals_solo": same,
+                     "oracle_sample_ok": oracle_ok}
+        log("config4 %s: %s" % (mode, res[mode]))
+    sc = res["screen"]
+    line = {
+        "metric": "GB/s text scanned (fraction of HBM peak); batched/served p50/p99 latency",
+        "value": sc["batched"]["GB/s"], "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": sc["batched"]["ms_per_batch"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+        "config": {"workload": "batched uneven instances: %d texts log-uniform 4 KiB..16 MiB (%d B total), "
+                               "alphabets {4,26,256}, 1..32 patterns m=4..64, half planted" % (len(insts), total_bytes),
+                   "instances": len(insts), "text_bytes": total_bytes, "results": res,
+                   "speedup_vs_one_launch_per_instance": round(
+                       sc["batched"]["GB/s"] / max(sc["one_launch_per_instance"]["GB/s"], 1e-9), 2)},
+    }
+    print(json.dumps(line), flush=True)
+
+
+# ---------------------------------------------------------------- config 5
+def bench_config5(args):
+    """Open-loop Poisson request streams against 64 resident corpora served by
+    the continuous-batching server; latency submit -> done, throughput."""
+    import threading
+    import numpy as np
+    import torch
+    import rkgen
+    import paper_1810_01051_amd as rk
+    n = args.corpus_bytes
+    t0 = time.perf_counter()
+    corpora = [rkgen.config5_corpus(i, n) for i in range(args.corpora)]
+    torch.cuda.synchronize()
+    log("config5: %d corpora x %d bytes in %.1fs" % (len(corpora), n, time.perf_counter() - t0))
+    ctx = rk.Context(0)
+    if args.tune and os.path.exists(args.tune):
+        ctx.autotune_load(args.tune)
+
+    def materialise(specs):
+        # gather every sampled (offset, length) on the device, one copy back
+        idx_c, idx_o, idx_m = [], [], []
+        for (_, c, pats) in specs:
+            for p in pats:
+                if isinstance(p, tuple):
+                    idx_c.append(c)
+                    idx_o.append(p[0])
+                    idx_m.append(p[1])
+        got = {}
+        if idx_c:
+            cs, os_, ms = np.array(idx_c), np.array(idx_o), np.array(idx_m)
+            for c in np.unique(cs):
+                sel = np.nonzero(cs == c)[0]
+                starts = torch.from_numpy(os_[sel]).to("cuda:0")
+                lens = torch.from_numpy(ms[sel]).to("cuda:0")
+                ends = torch.cumsum(lens, 0)
+                tot = int(ends[-1])
+                seg = torch.repeat_interleave(torch.arange(len(sel), device="cuda:0"), lens)
+                pos = starts[seg] + torch.arange(tot, device="cuda:0") - (ends - lens)[seg]
+                blob = corpora[int(c)][pos].cpu().numpy()
+                e = ends.cpu().numpy()
+                for q, i in enumerate(sel):
+                    got[int(i)] = blob[e[q] - ms[i]:e[q]].tobytes()
+        out, k = [], 0
+        for (t, c, pats) in specs:
+            ps = []
+            for p in pats:
+                if isinstance(p, tuple):
+                    ps.append(got[k])
+                    k += 1
+                else:
+                    ps.append(p)
+            out.append((t, c, ps))
+        return out
+
+    def run(rate, warm, dur, **srv_kw):
+        specs = rkgen.config5_request_specs(rate, warm + dur, n, corpora=len(corpora), seed_sub=int(rate))
+        reqs = materialise(specs)
+        srv = rk.Server(ctx, mode=args.mode, **srv_kw)
+        for c in corpora:
+            srv.add_corpus(c)
+        rids = [None] * len(reqs)
+        lat = {}
+        stop = threading.Event()
+
+        def releaser():
+            i = 0
+            while i < len(reqs):
+                if rids[i] is None:
+                    if stop.is_set():
+                        return
+                    time.sleep(0.0002)
+                    continue
+                res = srv.wait(rids[i], timeout=600, fetch=False)
+                lat[i] = (res["t_done"] - res["t_submit"], res["status"], int(res["offsets"][-1]))
+                srv.release(rids[i])
+                i += 1
+
+        th = threading.Thread(target=releaser)
+        th.start()
+        t_begin = time.perf_counter()
+        for i, (t, c, pats) in enumerate(reqs):
+            d = t_begin + t - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            rids[i] = srv.submit(c, pats)
+        t_sub_end = time.perf_counter()
+        srv.drain()
+        th.join()
+        t_end = time.perf_counter()
+        st = srv.stats()
+        srv.close()
+        meas = [i for i, (t, _, _) in enumerate(reqs) if t >= warm]
+        ls = np.array([lat[i][0] for i in meas]) * 1e3
+        ok = all(lat[i][1] == 0 for i in lat)
+        hits = sum(lat[i][2] for i in meas)
+        # measured window: from the first measured arrival until the last measured request is done
+        tput = len(meas) / max(t_end - (t_begin + warm), 1e-9)
+        return {"offered_req_s": rate, "requests": len(meas), "achieved_req_s": round(tput, 1),
+                "p50_ms": round(float(np.percentile(ls, 50)), 2), "p99_ms": round(float(np.percentile(ls, 99)), 2),
+                "mean_ms": round(float(ls.mean()), 2), "all_ok": bool(ok), "hits": int(hits),
+                "steps": st["steps"], "merged_patterns": st["merged_patterns"],
+                "request_patterns": st["request_patterns"],
+                "scan_GB/s_while_busy": round(st["bytes_scanned"] / max(st["busy_s"], 1e-9) / 1e9, 1),
+                "admission_waits": st["admission_waits"], "submit_lag_s": round(t_sub_end - t_begin - warm - dur, 3)}
+
+    results = {}
+    for rate in args.rates:
+        results["batched_%d" % rate] = run(rate, args.warm5, args.duration5, arena_bytes=args.arena,
+                                           max_inflight=args.inflight, use_graphs=True)
+        log("config5 batched %d: %s" % (rate, results["batched_%d" % rate]))
+    base_rate = min(args.rates)
+    results["one_request_per_launch_%d" % base_rate] = run(base_rate, args.warm5, args.duration5,
+                                                            arena_bytes=args.arena, max_inflight=1,
+                                                            max_step_requests=1, use_graphs=False)
+    log("config5 unbatched: %s" % results["one_request_per_launch_%d" % base_rate])
+    top = results["batched_%d" % max(args.rates)]
+    line = {
+        "metric": "GB/s text scanned (fraction of HBM peak); batched/served p50/p99 latency",
+        "value": top["achieved_req_s"], "unit": "req/s", "n_gpus": 1, "steps": top["steps"], "warmup": 0,
+        "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u8", "data": "synthetic",
+        "config": {"workload": "serving: Poisson requests over %d resident corpora of %d B (Zipf word text), "
+                               "1..256 patterns m=4..64 per request" % (len(corpora), n),
+                   "mode": args.mode, "results": results},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -137,6 +364,17 @@ def main():
     ap.add_argument("--tune", default=os.path.join(ROOT, "profiles", "autotune_gfx950.json"))
     ap.add_argument("--cfg", type=int, default=-1, help="force a scan geometry (rk_tile_cfg index)")
     ap.add_argument("--grid", type=int, default=0, help="force the persistent grid size")
+    ap.add_argument("--workload", default="config2", choices=["config2", "config4", "config5"],
+                    help="config2 (default): the single-pattern DNA scan; config4: batched uneven "
+                         "instances; config5: serving")
+    ap.add_argument("--count4", type=int, default=4096, help="config4 instances")
+    ap.add_argument("--corpora", type=int, default=64, help="config5 corpora")
+    ap.add_argument("--corpus-bytes", type=int, default=1 << 30, help="config5 bytes per corpus")
+    ap.add_argument("--rates", type=float, nargs="+", default=[500, 2000, 8000], help="config5 offered req/s")
+    ap.add_argument("--warm5", type=float, default=1.0)
+    ap.add_argument("--duration5", type=float, default=10.0)
+    ap.add_argument("--arena", type=int, default=32 << 30, help="config5 server output arena bytes")
+    ap.add_argument("--inflight", type=int, default=2, help="config5 steps in flight")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (for PMC byte-counter calibration)")
     args = ap.parse_args()
@@ -159,6 +397,11 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"calib_copy_bytes": 1 << 30, "launches": 3}))
         return
+
+    if args.workload == "config4":
+        return bench_config4(args)
+    if args.workload == "config5":
+        return bench_config5(args)
 
     import rkgen
     import paper_1810_01051_amd as rk

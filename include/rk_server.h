@@ -7,9 +7,11 @@
  * requests that are waiting: per corpus it merges their patterns (identical
  * patterns are searched once), and a step scans all its corpora in one
  * persistent launch (the batch path of rk.h).  Each step runs count ->
- * admission -> collect: the count pass gives the exact output size, the step
- * is admitted when that much of the output arena is free, then collect writes
- * every hit into its slice and the server splits the results per request.
+ * admission -> collect -> split: the count pass gives the exact output size,
+ * the step is admitted when the output arena can hold it, collect writes every
+ * hit, and a device copy gives each request a contiguous slice of the arena
+ * (results stay in device memory until the client releases them; the host
+ * gets per-pattern offsets, and positions on demand).
  * Several steps are in flight at once on separate streams, so requests that
  * arrive while others run on the device are admitted as slots and arena space
  * free up.  Launches of a step are replayed from HIP graphs captured once per
@@ -30,7 +32,8 @@ extern "C" {
 typedef struct rk_server rk_server;
 
 typedef struct {
-  uint64_t arena_bytes;        /* device memory for hits of steps in flight (default 1 GiB) */
+  uint64_t arena_bytes;        /* device memory for hits of steps in flight and of finished,
+                                  unreleased requests (default 4 GiB) */
   uint32_t max_inflight;       /* steps in flight on the device, 1..8 (default 2) */
   uint32_t max_step_requests;  /* requests merged into one step (default 4096) */
   uint32_t max_step_patterns;  /* merged patterns per step (default 262144) */
@@ -45,7 +48,8 @@ typedef struct {
   rk_status status;            /* RK_OK done, RK_EBUSY pending, RK_ECANCELED, or the step's error */
   uint32_t k;                  /* patterns of the request */
   const uint64_t *offsets;     /* host, k+1 entries; valid until rk_server_release */
-  const uint64_t *positions;   /* host, offsets[k] entries, per pattern ascending */
+  const uint64_t *positions_dev; /* device (server arena), offsets[k] entries, per pattern
+                                    ascending; valid until rk_server_release */
   double t_submit, t_start, t_done; /* seconds on the server's monotonic clock */
   uint64_t step;               /* step that served the request */
 } rk_result_view;
@@ -81,7 +85,10 @@ rk_status rk_server_poll(rk_server *srv, uint64_t req_id, rk_result_view *out);
 rk_status rk_server_wait(rk_server *srv, uint64_t req_id, double timeout_s, rk_result_view *out);
 /* Cancels a request that has not been put into a step (RK_EBUSY otherwise). */
 rk_status rk_server_cancel(rk_server *srv, uint64_t req_id);
-/* Frees a finished request's results. */
+/* Copies a finished request's positions (offsets[k] entries) to host memory;
+ * cap = entries available at positions_host.  Synchronous. */
+rk_status rk_server_fetch(rk_server *srv, uint64_t req_id, uint64_t *positions_host, uint64_t cap);
+/* Frees a finished request's results (its arena slice becomes free). */
 rk_status rk_server_release(rk_server *srv, uint64_t req_id);
 /* Blocks until every submitted request is finished. */
 rk_status rk_server_drain(rk_server *srv);

@@ -54,7 +54,7 @@ class RkServerCfg(ctypes.Structure):
 
 
 class RkResultView(ctypes.Structure):
-    _fields_ = [("status", ctypes.c_int), ("k", ctypes.c_uint32), ("offsets", c_u64p), ("positions", c_u64p),
+    _fields_ = [("status", ctypes.c_int), ("k", ctypes.c_uint32), ("offsets", c_u64p), ("positions_dev", c_void),
                 ("t_submit", ctypes.c_double), ("t_start", ctypes.c_double), ("t_done", ctypes.c_double),
                 ("step", ctypes.c_uint64)]
 
@@ -79,6 +79,7 @@ SIGNATURES = {
     "rk_server_wait": (ctypes.c_int, [c_void, ctypes.c_uint64, ctypes.c_double, ctypes.POINTER(RkResultView)]),
     "rk_server_cancel": (ctypes.c_int, [c_void, ctypes.c_uint64]),
     "rk_server_release": (ctypes.c_int, [c_void, ctypes.c_uint64]),
+    "rk_server_fetch": (ctypes.c_int, [c_void, ctypes.c_uint64, c_void, ctypes.c_uint64]),
     "rk_server_drain": (ctypes.c_int, [c_void]),
     "rk_server_get_stats": (ctypes.c_int, [c_void, ctypes.POINTER(RkServerStats)]),
     "rk_server_reset_stats": (ctypes.c_int, [c_void]),

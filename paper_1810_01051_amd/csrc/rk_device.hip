@@ -214,6 +214,27 @@ __device__ __forceinline__ uint64_t exact_step(uint64_t s, uint32_t in, uint32_t
   return mul256_lazy(s) + in + (kQ - rot61(out, r));
 }
 
+// The same step with the 32-bit halves spelled out and the outgoing term
+// specialised on where out * 2^r lands in the 61-bit word (r = 8m mod 61 is
+// fixed per group):  OUTK 0: bits r..r+7 in the low word (r <= 24),
+// 1: in the high word (32 <= r <= 53), 2: anywhere (general rotation).
+//   256 s mod q = ((s << 8) & q) + (s >> 53): the low byte of s << 8 is free
+//   for the entering byte; q - v = q ^ v for v <= q.
+// Bounds as exact_step: s < 2^63 in, s < 2^62 + 2^11 out.
+template <int OUTK>
+__device__ __forceinline__ uint64_t exact_step_k(uint64_t s, uint32_t in, uint32_t out, uint32_t r) {
+  const uint32_t lo = (uint32_t)s, hi = (uint32_t)(s >> 32);
+  const uint32_t alo = (lo << 8) | in;
+  const uint32_t ahi = __builtin_amdgcn_alignbit(hi, lo, 24) & 0x1FFFFFFFu;
+  uint64_t neg;
+  if (OUTK == 0) neg = (0x1FFFFFFFull << 32) | (uint64_t)(uint32_t)~(out << r);
+  else if (OUTK == 1) neg = ((uint64_t)(0x1FFFFFFFu ^ (out << (r - 32))) << 32) | 0xFFFFFFFFull;
+  else neg = kQ - rot61(out, r);
+  return ((((uint64_t)ahi << 32) | alo) + neg) + (hi >> 21);
+}
+
+__device__ __forceinline__ int out_kind(uint32_t r) { return r <= 24 ? 0 : ((r >= 32 && r <= 53) ? 1 : 2); }
+
 // Out-stream: the byte leaving window i (the thread's i-th window end) sits m
 // bytes before the entering one.  It is read as aligned LDS dwords starting
 // o = 4*ceil(m/4) bytes before the thread's first window end and realigned by
@@ -231,7 +252,7 @@ __device__ __forceinline__ OutStream out_stream(const uint8_t *mine, uint32_t m)
   return os;
 }
 
-template <int C, bool ANY, bool TABLE>
+template <int C, bool ANY, bool TABLE, int NT, int OUTK>
 __device__ __forceinline__ void pass_exact(const uint32_t *tw, OutStream os, uint32_t m, uint32_t r, const uint32_t *tg,
                                            const uint32_t *fp, uint32_t fmask, uint64_t &any, Bits<C> &bits) {
   uint32_t w[16 + C / 4];
@@ -245,7 +266,7 @@ __device__ __forceinline__ void pass_exact(const uint32_t *tw, OutStream os, uin
       ow = __builtin_amdgcn_alignbyte(dhi, dlo, os.sh);
       dlo = dhi;
     }
-    s = exact_step(s, byte_at(w, 64 + i), (ow >> (8 * (i & 3))) & 0xFFu, r);
+    s = exact_step_k<OUTK>(s, byte_at(w, 64 + i), (ow >> (8 * (i & 3))) & 0xFFu, r);
     if (TABLE) {
       const uint32_t h = (uint32_t)canon(s);
       const uint32_t e = fp[h & fmask];
@@ -255,12 +276,26 @@ __device__ __forceinline__ void pass_exact(const uint32_t *tw, OutStream os, uin
     } else {
       // lazy state s = H + j*q for j in {0,1,2}; the host lists the low words
       const uint32_t lo = (uint32_t)s;
-      if (ANY)
-        any_or(any, ballot(lo == tg[0]) | ballot(lo == tg[1]) | ballot(lo == tg[2]) | ballot(lo == tg[3]));
-      else
-        put_bit<C>(bits, acc, i, lo == tg[0] || lo == tg[1] || lo == tg[2] || lo == tg[3]);
+      if (ANY) {
+        uint64_t b = ballot(lo == tg[0]) | ballot(lo == tg[1]);
+        if (NT > 2) b |= ballot(lo == tg[2]) | ballot(lo == tg[3]);
+        any_or(any, b);
+      } else {
+        bool c = lo == tg[0] || lo == tg[1];
+        if (NT > 2) c = c || lo == tg[2] || lo == tg[3];
+        put_bit<C>(bits, acc, i, c);
+      }
     }
   }
+}
+
+template <int C, bool ANY, bool TABLE, int NT>
+__device__ __forceinline__ void pass_exact_r(const uint32_t *tw, OutStream os, uint32_t m, uint32_t r, const uint32_t *tg,
+                                             const uint32_t *fp, uint32_t fmask, uint64_t &any, Bits<C> &bits) {
+  const int k = out_kind(r);
+  if (k == 0) pass_exact<C, ANY, TABLE, NT, 0>(tw, os, m, r, tg, fp, fmask, any, bits);
+  else if (k == 1) pass_exact<C, ANY, TABLE, NT, 1>(tw, os, m, r, tg, fp, fmask, any, bits);
+  else pass_exact<C, ANY, TABLE, NT, 2>(tw, os, m, r, tg, fp, fmask, any, bits);
 }
 
 // kDump: canonical rolling hash of windows x = e - m + 1 with x % stride == 0.
@@ -328,8 +363,12 @@ __device__ __forceinline__ void run_pass(const BucketDesc &D, const uint32_t *tw
       else pass_table_screen<C, 8, ANY>(tw, fp, D.fp_mask, any, bits);
     }
   } else {
-    if (D.kind == kListExact) pass_exact<C, ANY, false>(tw, os, D.m, r, D.tgt, fp, D.fp_mask, any, bits);
-    else pass_exact<C, ANY, true>(tw, os, D.m, r, D.tgt, fp, D.fp_mask, any, bits);
+    if (D.kind == kListExact) {
+      if ((D.shift >> 8) <= 2u) pass_exact_r<C, ANY, false, 2>(tw, os, D.m, r, D.tgt, fp, D.fp_mask, any, bits);
+      else pass_exact_r<C, ANY, false, 4>(tw, os, D.m, r, D.tgt, fp, D.fp_mask, any, bits);
+    } else {
+      pass_exact_r<C, ANY, true, 2>(tw, os, D.m, r, D.tgt, fp, D.fp_mask, any, bits);
+    }
   }
 }
 
@@ -1067,6 +1106,28 @@ __global__ __launch_bounds__(256) void stream_read_kernel(const uint4 *data, uin
 
 hipError_t launch_stream_read(const void *data, uint64_t n, uint32_t *out, uint32_t grid, hipStream_t s) {
   hipLaunchKernelGGL(stream_read_kernel, dim3(grid), dim3(256), 0, s, (const uint4 *)data, n / 16, out);
+  return hipGetLastError();
+}
+
+}  // namespace rk
+
+namespace rk {
+
+// ------------------------------------------------------- segmented copy
+// dst_k[0..len_k) = src[src_off_k .. src_off_k + len_k) for every segment;
+// the server uses it to give each request a contiguous copy of its patterns'
+// hit lists out of a merged step.  Segments are at most 65536 entries long.
+__global__ __launch_bounds__(256) void segment_copy_kernel(const uint64_t *src, const CopySeg *segs, uint32_t nseg) {
+  for (uint32_t s = blockIdx.x; s < nseg; s += gridDim.x) {
+    const CopySeg g = segs[s];
+    for (uint64_t i = threadIdx.x; i < g.len; i += 256) g.dst[i] = src[g.src_off + i];
+  }
+}
+
+hipError_t launch_segment_copy(const uint64_t *src, const CopySeg *segs, uint32_t nseg, hipStream_t s) {
+  if (nseg == 0) return hipSuccess;
+  const uint32_t grid = nseg < 4096 ? nseg : 4096;
+  hipLaunchKernelGGL(segment_copy_kernel, dim3(grid), dim3(256), 0, s, src, segs, nseg);
   return hipGetLastError();
 }
 

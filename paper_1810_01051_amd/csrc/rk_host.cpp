@@ -165,6 +165,7 @@ static bool emit_group(const GroupIn &G, int mode, std::vector<uint8_t> &body, B
     if (lazy.size() <= 4) {
       D.kind = kListExact;
       for (int j = 0; j < 4; ++j) D.tgt[j] = lazy[j < (int)lazy.size() ? j : 0];
+      D.shift = (uint32_t)(lazy.size() <= 2 ? 2u : 4u) << 8;  // compare count the kernel unrolls
     } else {
       D.kind = kTableExact;
       for (uint64_t H : dist) fpkeys.push_back((uint32_t)H);

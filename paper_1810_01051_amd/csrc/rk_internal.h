@@ -104,6 +104,13 @@ struct ScanParams {
   uint64_t dump_cap;
 };
 
+// One segment of the server's per-request copy of a merged step's hits.
+struct CopySeg {
+  uint64_t src_off;  // first entry in the merged positions
+  uint64_t *dst;     // destination (device)
+  uint64_t len;      // entries
+};
+
 // Host-side geometry table (workgroup size, windows per thread).
 struct TileCfg {
   uint32_t wg;

@@ -41,7 +41,8 @@ struct Request {
   std::vector<uint8_t> bytes;
   std::vector<uint64_t> offs;
   rk_status status = RK_EBUSY;
-  std::vector<uint64_t> res_offsets, res_positions;
+  std::vector<uint64_t> res_offsets;  // host, k+1
+  uint64_t out_off = 0, out_size = 0; // the request's positions in the arena (bytes)
   std::vector<uint32_t> gpid;  // merged pattern id of each pattern within its step
   double t_submit = 0, t_start = 0, t_done = 0;
   uint64_t step = 0;
@@ -96,11 +97,11 @@ struct Arena {
   }
 };
 
-enum SlotState { kIdle, kCounting, kCounted, kCollecting };
+enum SlotState { kIdle, kCounting, kCounted, kCollecting, kDemuxing };
 
 struct Slot {
   hipStream_t stream = nullptr;
-  hipEvent_t ev_count = nullptr, ev_collect = nullptr;
+  hipEvent_t ev_count = nullptr, ev_collect = nullptr, ev_demux = nullptr;
   SlotState state = kIdle;
   rk_plan plan;
   void *dplan = nullptr;
@@ -109,14 +110,21 @@ struct Slot {
   uint64_t scratch_cap = 0;
   uint8_t *hstage = nullptr;  // pinned: plan bytes for the upload
   uint64_t hstage_cap = 0;
-  uint64_t *hres = nullptr;   // pinned: offsets then positions of the step
+  uint64_t *hres = nullptr;   // pinned: merged per-pattern offsets of the step
   uint64_t hres_cap = 0;      // bytes
+  CopySeg *hsegs = nullptr;   // pinned: demux segments
+  uint64_t hsegs_cap = 0;
+  void *dsegs = nullptr;      // device copy of the segments
+  uint64_t dsegs_cap = 0;
+  uint32_t max_mult = 1;      // largest number of request patterns sharing one merged pattern
   uint64_t *hctr = nullptr;   // pinned: total, overflow count
   hipGraphExec_t gcount = nullptr, gcollect = nullptr;
   std::vector<Request *> reqs;
   uint64_t step_id = 0, n_total = 0, total = 0, plan_bytes = 0;
   uint32_t ovf = 0;
-  uint64_t arena_off = 0, arena_size = 0;
+  uint64_t arena_off = 0, arena_size = 0;  // merged output + work of the step
+  uint64_t res_off = 0, res_size = 0;      // reservation for the per-request copies
+  uint64_t merged_pos_off = 0;             // merged positions inside the arena
   double t_start = 0;
 };
 
@@ -301,10 +309,16 @@ static rk_status start_step(rk_server *S, Slot &sl, std::unique_lock<std::mutex>
     nbytes += I.n;
     inst.push_back(I);
   }
+  std::vector<uint32_t> mult(kt, 0);
   for (size_t i = 0; i < take.size(); ++i) {
     take[i]->gpid.resize(take[i]->k);
-    for (uint32_t j = 0; j < take[i]->k; ++j) take[i]->gpid[j] = base[local[i][j].first] + local[i][j].second;
+    for (uint32_t j = 0; j < take[i]->k; ++j) {
+      take[i]->gpid[j] = base[local[i][j].first] + local[i][j].second;
+      ++mult[take[i]->gpid[j]];
+    }
   }
+  sl.max_mult = 1;
+  for (uint32_t c : mult) sl.max_mult = std::max(sl.max_mult, c);
   // host plan
   sl.plan = rk_plan();
   std::vector<uint8_t> blob;
@@ -371,36 +385,44 @@ static rk_status start_step(rk_server *S, Slot &sl, std::unique_lock<std::mutex>
 }
 
 // Admission and collect of a counted step (mu held).  Returns false if the
-// arena cannot hold it yet.
+// arena cannot hold it yet.  The step needs its merged output (per-pattern
+// offsets, positions, sort work) until the per-request copies are made, and
+// room for those copies (at most max_mult times the merged positions).
 static bool try_collect(rk_server *S, Slot &sl, std::unique_lock<std::mutex> &lk) {
   const uint32_t k = sl.plan.k_total;
   const uint64_t off_b = aup((uint64_t)(k + 1) * 8, 256), pos_b = aup(std::max<uint64_t>(sl.total, 1) * 8, 256);
   const uint64_t work_b = aup(work_bytes_for(&sl.plan, sl.total), 256);
   const uint64_t need = off_b + pos_b + work_b;
+  const uint64_t need_req = aup((uint64_t)sl.max_mult * sl.total * 8 + 256ull * sl.reqs.size(), 256);
   rk_status st = RK_OK;
-  if (need > S->arena.cap) {
-    st = set_err(S->ctx, RK_ENOSPACE, "step needs %llu arena bytes (arena %llu)", (unsigned long long)need,
-                 (unsigned long long)S->arena.cap);
+  if (need + need_req > S->arena.cap) {
+    st = set_err(S->ctx, RK_ENOSPACE, "step needs %llu arena bytes (arena %llu)",
+                 (unsigned long long)(need + need_req), (unsigned long long)S->arena.cap);
   } else {
-    uint64_t off;
+    uint64_t off, roff;
     if (!S->arena.alloc(need, &off)) return false;
+    if (!S->arena.alloc(need_req, &roff)) {
+      S->arena.release(off, need);
+      return false;
+    }
     sl.arena_off = off;
     sl.arena_size = need;
+    sl.res_off = roff;
+    sl.res_size = need_req;
+    sl.merged_pos_off = off + off_b;
     lk.unlock();
     uint8_t *base = (uint8_t *)S->arena_dev + off;
     uint64_t *doff = (uint64_t *)base, *dpos = (uint64_t *)(base + off_b);
     void *work = work_b ? base + off_b + pos_b : nullptr;
-    hipError_t e = ensure_pinned(&sl.hres, &sl.hres_cap, (uint64_t)(k + 1 + sl.total) * 8);
-    if (e != hipSuccess) st = hip_err(S->ctx, e, "result staging");
+    hipError_t e = ensure_pinned(&sl.hres, &sl.hres_cap, (uint64_t)(k + 1) * 8);
+    if (e != hipSuccess) st = hip_err(S->ctx, e, "offset staging");
     if (st == RK_OK)
       st = run_maybe_graph(S, sl, &sl.gcollect, [&]() -> rk_status {
         rk_status s2 = collect_enqueue_known(S->ctx, &sl.plan, 0, sl.scratch, sl.scratch_cap, work, work_b, doff,
                                              dpos, std::max<uint64_t>(sl.total, 1), sl.total, sl.ovf, sl.stream);
         if (s2 != RK_OK) return s2;
         hipError_t e2 = hipMemcpyAsync(sl.hres, doff, (uint64_t)(k + 1) * 8, hipMemcpyDeviceToHost, sl.stream);
-        if (e2 == hipSuccess && sl.total)
-          e2 = hipMemcpyAsync(sl.hres + k + 1, dpos, sl.total * 8, hipMemcpyDeviceToHost, sl.stream);
-        return e2 == hipSuccess ? RK_OK : hip_err(S->ctx, e2, "result copy");
+        return e2 == hipSuccess ? RK_OK : hip_err(S->ctx, e2, "offset copy");
       });
     if (st == RK_OK) {
       e = hipEventRecord(sl.ev_collect, sl.stream);
@@ -412,6 +434,7 @@ static bool try_collect(rk_server *S, Slot &sl, std::unique_lock<std::mutex> &lk
       return true;
     }
     S->arena.release(sl.arena_off, sl.arena_size);
+    S->arena.release(sl.res_off, sl.res_size);
   }
   for (Request *r : sl.reqs) finish_request(S, r, st);
   sl.reqs.clear();
@@ -421,10 +444,26 @@ static bool try_collect(rk_server *S, Slot &sl, std::unique_lock<std::mutex> &lk
   return true;
 }
 
-// Splits a collected step's hits per request (mu held).
-static void finish_step(rk_server *S, Slot &sl) {
-  const uint32_t k = sl.plan.k_total;
-  const uint64_t *off = sl.hres, *pos = sl.hres + k + 1;
+static void fail_step(rk_server *S, Slot &sl, rk_status st) {
+  for (Request *r : sl.reqs) finish_request(S, r, st);
+  sl.reqs.clear();
+  if (sl.arena_size) S->arena.release(sl.arena_off, sl.arena_size);
+  if (sl.res_size) S->arena.release(sl.res_off, sl.res_size);
+  sl.arena_size = sl.res_size = 0;
+  sl.state = kIdle;
+  if (--S->inflight == 0) S->busy_s += now_s() - S->busy_since;
+  S->cv_done.notify_all();
+}
+
+// Collected step: gives every request a contiguous slice of the arena and
+// enqueues the device copy of its patterns' hit lists (mu held).
+static void start_demux(rk_server *S, Slot &sl) {
+  const uint64_t *off = sl.hres;
+  constexpr uint64_t kSeg = 65536;
+  std::vector<CopySeg> segs;
+  // the reservation becomes the per-request slices (first fit lands inside it)
+  S->arena.release(sl.res_off, sl.res_size);
+  sl.res_size = 0;
   for (Request *r : sl.reqs) {
     r->res_offsets.assign(r->k + 1, 0);
     uint64_t tot = 0;
@@ -433,17 +472,53 @@ static void finish_step(rk_server *S, Slot &sl) {
       tot += off[g + 1] - off[g];
       r->res_offsets[j + 1] = tot;
     }
-    r->res_positions.resize(tot);
+    r->out_size = tot * 8;
+    r->out_off = 0;
+    if (tot && !S->arena.alloc(r->out_size, &r->out_off)) {
+      fail_step(S, sl, set_err(S->ctx, RK_ENOSPACE, "request slices do not fit the reservation"));
+      return;
+    }
+    uint64_t *dst = (uint64_t *)((uint8_t *)S->arena_dev + r->out_off);
     for (uint32_t j = 0; j < r->k; ++j) {
       const uint32_t g = r->gpid[j];
-      std::copy(pos + off[g], pos + off[g + 1], r->res_positions.begin() + r->res_offsets[j]);
+      for (uint64_t a = off[g]; a < off[g + 1]; a += kSeg) {
+        CopySeg cs;
+        cs.src_off = a;
+        cs.dst = dst + r->res_offsets[j] + (a - off[g]);
+        cs.len = std::min<uint64_t>(kSeg, off[g + 1] - a);
+        segs.push_back(cs);
+      }
     }
+  }
+  hipError_t e = ensure_pinned(&sl.hsegs, &sl.hsegs_cap, segs.size() * sizeof(CopySeg) + 64);
+  if (e == hipSuccess) e = ensure_dev(&sl.dsegs, &sl.dsegs_cap, segs.size() * sizeof(CopySeg) + 64);
+  if (e == hipSuccess && !segs.empty()) {
+    memcpy(sl.hsegs, segs.data(), segs.size() * sizeof(CopySeg));
+    e = hipMemcpyAsync(sl.dsegs, sl.hsegs, segs.size() * sizeof(CopySeg), hipMemcpyHostToDevice, sl.stream);
+    if (e == hipSuccess)
+      e = launch_segment_copy((const uint64_t *)((uint8_t *)S->arena_dev + sl.merged_pos_off),
+                              (const CopySeg *)sl.dsegs, (uint32_t)segs.size(), sl.stream);
+  }
+  if (e == hipSuccess) e = hipEventRecord(sl.ev_demux, sl.stream);
+  if (e != hipSuccess) {
+    for (Request *r : sl.reqs)
+      if (r->out_size) S->arena.release(r->out_off, r->out_size), r->out_size = 0;
+    fail_step(S, sl, hip_err(S->ctx, e, "demux"));
+    return;
+  }
+  sl.state = kDemuxing;
+}
+
+// Demuxed step: the merged output is freed, the requests are done (mu held).
+static void finish_step(rk_server *S, Slot &sl) {
+  for (Request *r : sl.reqs) {
     r->bytes.clear();
     r->bytes.shrink_to_fit();
     finish_request(S, r, RK_OK);
   }
   sl.reqs.clear();
   S->arena.release(sl.arena_off, sl.arena_size);
+  sl.arena_size = 0;
   sl.state = kIdle;
   if (--S->inflight == 0) S->busy_s += now_s() - S->busy_since;
   S->cv_done.notify_all();
@@ -463,12 +538,7 @@ static void scheduler(rk_server *S) {
           sl.state = kCounted;
           progress = true;
         } else if (q != hipErrorNotReady) {
-          rk_status st = hip_err(S->ctx, q, "count pass");
-          for (Request *r : sl.reqs) finish_request(S, r, st);
-          sl.reqs.clear();
-          sl.state = kIdle;
-          if (--S->inflight == 0) S->busy_s += now_s() - S->busy_since;
-          S->cv_done.notify_all();
+          fail_step(S, sl, hip_err(S->ctx, q, "count pass"));
         }
       }
       if (sl.state == kCounted) {
@@ -478,16 +548,21 @@ static void scheduler(rk_server *S) {
       if (sl.state == kCollecting) {
         const hipError_t q = hipEventQuery(sl.ev_collect);
         if (q == hipSuccess) {
+          start_demux(S, sl);
+          progress = true;
+        } else if (q != hipErrorNotReady) {
+          fail_step(S, sl, hip_err(S->ctx, q, "collect pass"));
+        }
+      }
+      if (sl.state == kDemuxing) {
+        const hipError_t q = hipEventQuery(sl.ev_demux);
+        if (q == hipSuccess) {
           finish_step(S, sl);
           progress = true;
         } else if (q != hipErrorNotReady) {
-          rk_status st = hip_err(S->ctx, q, "collect pass");
-          for (Request *r : sl.reqs) finish_request(S, r, st);
-          sl.reqs.clear();
-          S->arena.release(sl.arena_off, sl.arena_size);
-          sl.state = kIdle;
-          if (--S->inflight == 0) S->busy_s += now_s() - S->busy_since;
-          S->cv_done.notify_all();
+          for (Request *r : sl.reqs)
+            if (r->out_size) S->arena.release(r->out_off, r->out_size), r->out_size = 0;
+          fail_step(S, sl, hip_err(S->ctx, q, "demux copy"));
         }
       }
     }
@@ -521,7 +596,7 @@ extern "C" {
 
 void rk_server_cfg_default(rk_server_cfg *cfg) {
   if (!cfg) return;
-  cfg->arena_bytes = 1ull << 30;
+  cfg->arena_bytes = 4ull << 30;
   cfg->max_inflight = 2;
   cfg->max_step_requests = 4096;
   cfg->max_step_patterns = 262144;
@@ -565,6 +640,7 @@ rk_status rk_server_create(rk_ctx *ctx, const rk_server_cfg *cfg_in, rk_server *
     e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.ev_count, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.ev_collect, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.ev_demux, hipEventDisableTiming);
     if (e == hipSuccess) e = hipHostMalloc((void **)&sl.hctr, 64, hipHostMallocDefault);
     if (e != hipSuccess) break;
   }
@@ -631,11 +707,12 @@ rk_status rk_server_submit(rk_server *S, uint32_t corpus, const uint8_t *bytes, 
   return RK_OK;
 }
 
-static void fill_view(const Request *r, rk_result_view *out) {
+static void fill_view(const rk_server *S, const Request *r, rk_result_view *out) {
   out->status = r->status;
   out->k = r->k;
   out->offsets = r->res_offsets.empty() ? nullptr : r->res_offsets.data();
-  out->positions = r->res_positions.empty() ? nullptr : r->res_positions.data();
+  out->positions_dev = (r->status == RK_OK && r->out_size) ? (const uint64_t *)((uint8_t *)S->arena_dev + r->out_off)
+                                                           : nullptr;
   out->t_submit = r->t_submit;
   out->t_start = r->t_start;
   out->t_done = r->t_done;
@@ -647,7 +724,7 @@ rk_status rk_server_poll(rk_server *S, uint64_t id, rk_result_view *out) {
   std::lock_guard<std::mutex> g(S->mu);
   auto it = S->reqs.find(id);
   if (it == S->reqs.end()) return RK_EINVAL;
-  fill_view(it->second, out);
+  fill_view(S, it->second, out);
   return it->second->status == RK_EBUSY ? RK_EBUSY : RK_OK;
 }
 
@@ -660,7 +737,7 @@ rk_status rk_server_wait(rk_server *S, uint64_t id, double timeout_s, rk_result_
   const auto until = std::chrono::steady_clock::now() + std::chrono::duration<double>(timeout_s);
   while (r->status == RK_EBUSY)
     if (S->cv_done.wait_until(lk, until) == std::cv_status::timeout && r->status == RK_EBUSY) break;
-  fill_view(r, out);
+  fill_view(S, r, out);
   return r->status == RK_EBUSY ? RK_EBUSY : RK_OK;
 }
 
@@ -684,9 +761,33 @@ rk_status rk_server_release(rk_server *S, uint64_t id) {
   auto it = S->reqs.find(id);
   if (it == S->reqs.end()) return RK_EINVAL;
   if (it->second->status == RK_EBUSY) return RK_EBUSY;
+  if (it->second->out_size) S->arena.release(it->second->out_off, it->second->out_size);
   delete it->second;
   S->reqs.erase(it);
   return RK_OK;
+}
+
+rk_status rk_server_fetch(rk_server *S, uint64_t id, uint64_t *positions_host, uint64_t cap) {
+  if (!S) return RK_EINVAL;
+  uint64_t off = 0, bytes = 0;
+  {
+    std::lock_guard<std::mutex> g(S->mu);
+    auto it = S->reqs.find(id);
+    if (it == S->reqs.end()) return RK_EINVAL;
+    const Request *r = it->second;
+    if (r->status == RK_EBUSY) return RK_EBUSY;
+    if (r->status != RK_OK) return r->status;
+    off = r->out_off;
+    bytes = r->out_size;
+  }
+  if (bytes / 8 > cap) return RK_ENOSPACE;
+  if (bytes && !positions_host) return RK_EINVAL;
+  if (!bytes) return RK_OK;
+  hipSetDevice(S->device);
+  // the slice stays allocated until rk_server_release (the caller's)
+  return hipMemcpy(positions_host, (uint8_t *)S->arena_dev + off, bytes, hipMemcpyDeviceToHost) == hipSuccess
+             ? RK_OK
+             : RK_EDEVICE;
 }
 
 rk_status rk_server_drain(rk_server *S) {
@@ -757,6 +858,9 @@ void rk_server_destroy(rk_server *S) {
     drop_graphs(sl);
     if (sl.ev_count) hipEventDestroy(sl.ev_count);
     if (sl.ev_collect) hipEventDestroy(sl.ev_collect);
+    if (sl.ev_demux) hipEventDestroy(sl.ev_demux);
+    if (sl.hsegs) hipHostFree(sl.hsegs);
+    if (sl.dsegs) hipFree(sl.dsegs);
     if (sl.stream) hipStreamDestroy(sl.stream);
     if (sl.dplan) hipFree(sl.dplan);
     if (sl.scratch) hipFree(sl.scratch);

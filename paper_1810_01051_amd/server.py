@@ -61,30 +61,36 @@ class Server:
         check(st, None, "rk_server_submit")
         return int(rid.value)
 
-    @staticmethod
-    def _view_to_result(v: _lib.RkResultView):
+    def _view_to_result(self, rid: int, v: _lib.RkResultView, fetch: bool):
         k = v.k
         offs = np.ctypeslib.as_array(v.offsets, shape=(k + 1,)).copy() if v.offsets else np.zeros(1, np.uint64)
         tot = int(offs[-1])
-        pos = np.ctypeslib.as_array(v.positions, shape=(tot,)).copy() if tot else np.zeros(0, np.uint64)
-        return {"status": v.status, "offsets": offs, "positions": pos, "t_submit": v.t_submit,
-                "t_start": v.t_start, "t_done": v.t_done, "step": v.step}
+        res = {"status": v.status, "offsets": offs, "positions_dev": v.positions_dev, "t_submit": v.t_submit,
+               "t_start": v.t_start, "t_done": v.t_done, "step": v.step}
+        if fetch and v.status == 0:
+            pos = np.zeros(max(tot, 1), dtype=np.uint64)
+            check(self.lib.rk_server_fetch(self.h, int(rid), pos.ctypes.data_as(ctypes.c_void_p), pos.size), None,
+                  "rk_server_fetch")
+            res["positions"] = pos[:tot]
+        return res
 
-    def poll(self, rid: int):
+    def poll(self, rid: int, fetch: bool = True):
         v = _lib.RkResultView()
         st = self.lib.rk_server_poll(self.h, int(rid), ctypes.byref(v))
         if st == _lib.RK_EBUSY:
             return None
         check(st, None, "rk_server_poll")
-        return self._view_to_result(v)
+        return self._view_to_result(rid, v, fetch)
 
-    def wait(self, rid: int, timeout: float = 60.0):
+    def wait(self, rid: int, timeout: float = 60.0, fetch: bool = True):
+        """Blocks until request rid is done; with fetch, its positions are copied
+        to a numpy array (they live in device memory until release)."""
         v = _lib.RkResultView()
         st = self.lib.rk_server_wait(self.h, int(rid), float(timeout), ctypes.byref(v))
         if st == _lib.RK_EBUSY:
             raise TimeoutError("request %d not done after %.1fs" % (rid, timeout))
         check(st, None, "rk_server_wait")
-        return self._view_to_result(v)
+        return self._view_to_result(rid, v, fetch)
 
     def cancel(self, rid: int) -> int:
         return int(self.lib.rk_server_cancel(self.h, int(rid)))

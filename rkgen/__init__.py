@@ -235,6 +235,32 @@ def config5_corpus(index: int, n: int = 1 << 30, device="cuda:0", chunk_words: i
     return out
 
 
+def config5_request_specs(rate: float, duration: float, corpus_len: int, corpora: int = 64, kmax: int = 256,
+                          mmin: int = 4, mmax: int = 64, seed_sub: int = 0):
+    """Like config5_requests, but a sampled pattern is returned as its
+    (offset, length) in the target corpus, so that a caller holding the
+    corpora on the device can gather all sampled bytes at once.  Each request
+    is (t_arrival, corpus, [bytes | (offset, length), ...])."""
+    g = rng(5, 1000 + seed_sub)
+    t = 0.0
+    out = []
+    while True:
+        t += float(g.exponential(1.0 / rate))
+        if t >= duration:
+            break
+        c = int(g.integers(0, corpora))
+        k = int(g.integers(1, kmax + 1))
+        pats = []
+        for j in range(k):
+            m = int(g.integers(mmin, mmax + 1))
+            if j % 2 == 0:
+                pats.append((int(g.integers(0, corpus_len - m + 1)), m))
+            else:
+                pats.append(LOWER[g.integers(0, 26, size=m, dtype=np.uint8)].tobytes())
+        out.append((t, c, pats))
+    return out
+
+
 @dataclass
 class Request:
     t_arrival: float
