@@ -62,13 +62,14 @@ typedef enum {
 /* Scan modes.  Both give identical results.
  *   RK_MODE_EXACT : every window's d=256 / q=2^61-1 hash is rolled and tested
  *                   against the pattern-hash set; equal hashes are byte-checked.
- *   RK_MODE_SCREEN: every window first gets the paper's shift-and-add hash
- *                   h <- (h << s) + c taken mod 2^32 (shift s in {1,2,4,8}
- *                   chosen per pattern length, s = 1 being the paper's form);
- *                   windows whose shift-add hash is in the set get the exact
- *                   d=256 / q=2^61-1 hash, and equal exact hashes are
- *                   byte-checked.  A true occurrence always passes both tests,
- *                   so no occurrence is lost.
+ *   RK_MODE_SCREEN: every window gets the paper's shift-and-add hash
+ *                   h <- (h << s) + c taken mod 2^32 (the polynomial hash
+ *                   with d = 2^s, q = 2^32; shift s in {1,2,4,8} chosen per
+ *                   pattern length so that s*m >= 32, s = 1 being the paper's
+ *                   form), tested against the set of the patterns' shift-add
+ *                   hashes; windows in the set are byte-checked against the
+ *                   patterns with that hash.  A true occurrence always passes
+ *                   the test, so no occurrence is lost.
  *   RK_MODE_AUTO  : RK_MODE_SCREEN. */
 typedef enum { RK_MODE_AUTO = 0, RK_MODE_EXACT = 1, RK_MODE_SCREEN = 2 } rk_mode;
 

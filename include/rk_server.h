@@ -4,14 +4,16 @@
  * Corpora stay resident in device memory.  Clients submit searches (a corpus
  * id and a pattern set, the problem of Sec. 1 of Shah & Oza: every occurrence
  * of every pattern) from any thread.  A scheduler thread forms steps from the
- * requests that are waiting: per corpus it merges their patterns (identical
- * patterns are searched once), and a step scans all its corpora in one
- * persistent launch (the batch path of rk.h).  Each step runs count ->
- * admission -> collect -> split: the count pass gives the exact output size,
- * the step is admitted when the output arena can hold it, collect writes every
- * hit, and a device copy gives each request a contiguous slice of the arena
- * (results stay in device memory until the client releases them; the host
- * gets per-pattern offsets, and positions on demand).
+ * requests that are waiting: per corpus it concatenates their patterns
+ * (identical patterns share their bytes in the table image), and a step scans
+ * all its corpora in one persistent launch (the batch path of rk.h).  Each
+ * step runs count -> admission -> collect: the count pass gives the exact
+ * output size, the step is admitted when the output arena can hold it (a
+ * step too large for its share of the arena goes back to the queue and is
+ * split), and collect writes every hit sorted by merged pattern id, so that
+ * each request's result is a contiguous slice of the step's output without a
+ * copy (results stay in device memory until the client releases them; the
+ * host gets per-pattern offsets, and positions on demand).
  * Several steps are in flight at once on separate streams, so requests that
  * arrive while others run on the device are admitted as slots and arena space
  * free up.  Launches of a step are replayed from HIP graphs captured once per
@@ -66,6 +68,7 @@ typedef struct {
   uint32_t queue_depth;        /* requests waiting for a step */
   uint32_t inflight;           /* steps on the device */
   uint64_t admission_waits;    /* counted steps that waited for arena space */
+  uint64_t step_splits;        /* counted steps given back to the queue as too large */
 } rk_server_stats;
 
 /* Creates a server on ctx's device.  The server owns its streams, graphs,
@@ -88,7 +91,9 @@ rk_status rk_server_cancel(rk_server *srv, uint64_t req_id);
 /* Copies a finished request's positions (offsets[k] entries) to host memory;
  * cap = entries available at positions_host.  Synchronous. */
 rk_status rk_server_fetch(rk_server *srv, uint64_t req_id, uint64_t *positions_host, uint64_t cap);
-/* Frees a finished request's results (its arena slice becomes free). */
+/* Frees a finished request's results.  Its positions are a slice of its
+ * step's output block, which returns to the arena once every request of the
+ * step has been released. */
 rk_status rk_server_release(rk_server *srv, uint64_t req_id);
 /* Blocks until every submitted request is finished. */
 rk_status rk_server_drain(rk_server *srv);

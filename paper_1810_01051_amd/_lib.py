@@ -66,7 +66,7 @@ class RkServerStats(ctypes.Structure):
                 ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
                 ("max_ms", ctypes.c_double), ("busy_s", ctypes.c_double), ("arena_high_water", ctypes.c_uint64),
                 ("queue_depth", ctypes.c_uint32), ("inflight", ctypes.c_uint32),
-                ("admission_waits", ctypes.c_uint64)]
+                ("admission_waits", ctypes.c_uint64), ("step_splits", ctypes.c_uint64)]
 
 
 # name -> (restype, argtypes); the list mirrors include/rk.h and include/rk_server.h

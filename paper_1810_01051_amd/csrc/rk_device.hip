@@ -17,11 +17,11 @@
 //            state) and compared with the set;
 //   screen : the paper's shift-and-add hash h' = (h << s) + in mod 2^32 is
 //            rolled for every window (s*m >= 32, so bytes older than the window
-//            shift out and no out-term is needed); windows whose h is in the
-//            set are exact-hashed and looked up in the exact table.
-// In both, a candidate window is hashed again from scratch (Horner, canonical
-// value), looked up in the exact open-addressing table of its bucket and
-// confirmed byte by byte against every pattern chained under that hash.
+//            shift out and no out-term is needed) and compared with the set.
+// A candidate window (its hash passed the set test) is hashed again from
+// scratch (exact: Horner, canonical value; screen: shift-and-add), looked up
+// in the open-addressing table of its bucket and confirmed byte by byte
+// against every pattern chained under that hash.
 //
 // Hits are compacted with a block-wide prefix sum in ascending window order per
 // bucket into a per-tile staging slab; later kernels scan the tile counts,
@@ -32,14 +32,9 @@
 #include "rk_internal.h"
 
 // Build-time variants of the scan (the defaults are the measured best on gfx950):
-//   RK_PREFETCH  1: a workgroup issues the next tile's loads before processing
-//                   the current one; 0: loads, then waits, per tile.
 //   RK_MIN_ACC   1: single-target screen ORs matches through a VGPR minimum;
 //                0: through per-window wave ballots.
 //   RK_WAVES     >0: minimum waves per SIMD requested from the compiler.
-#ifndef RK_PREFETCH
-#define RK_PREFETCH 1
-#endif
 #ifndef RK_MIN_ACC
 #define RK_MIN_ACC 0
 #endif
@@ -71,6 +66,17 @@ __device__ __forceinline__ uint32_t byte_at(const uint32_t *w, int i) {
 __device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
 __device__ __forceinline__ uint64_t ballot(bool c) { return __builtin_amdgcn_ballot_w64(c); }
+
+// Workgroup barrier for LDS traffic only.  __syncthreads() would also wait for
+// every outstanding load-to-LDS of the next tile (the compiler's release fence
+// counts them), which would end the overlap of that tile's loads with the
+// current tile's work; the tile pipeline waits for them explicitly instead.
+__device__ __forceinline__ void wg_barrier() { __asm__ volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+// The same after this wave's loads-to-LDS have landed: after it, every wave's
+// share of the tile is visible.
+__device__ __forceinline__ void wg_barrier_loads() {
+  __asm__ volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
 
 // -------------------------------------------------------------- window tests
 // Each pass walks the C windows of the calling thread.  The register array w
@@ -106,23 +112,46 @@ __device__ __forceinline__ void put_bit(Bits<C> &bits, uint32_t &acc, int i, boo
   }
 }
 
-// Register values the compiler must treat as redefined here.  Every test
-// variant starts with it so that the byte extractions of the variants are not
-// merged and hoisted above the variant switch (which would keep every
-// extracted byte of every variant live at once).
-template <int NW>
-__device__ __forceinline__ void opaque(uint32_t *w) {
-#pragma unroll
-  for (int j = 0; j < NW; ++j) __asm__ volatile("" : "+v"(w[j]));
-}
+typedef __attribute__((address_space(3))) const uint32_t lds_word;
 
-// The thread's bytes, loaded from the LDS tile by each pass itself so that no
-// register copy of them stays live across buckets.
+// The thread's bytes, loaded from the LDS tile by each pass itself.  The
+// address goes through an empty asm first, so the compiler cannot share the
+// loads (nor the byte extractions that follow them) between the test variants
+// of a bucket and hoist them above the variant switch, which would keep every
+// extracted byte of every variant live at once; no register copy of the words
+// stays live across buckets either.
 template <int NW>
 __device__ __forceinline__ void load_words(uint32_t *w, const uint32_t *tw) {
+  lds_word *p = (lds_word *)tw;
+  __asm__ volatile("" : "+v"(p));
 #pragma unroll
-  for (int j = 0; j < NW; ++j) w[j] = tw[j];
-  opaque<NW>(w);
+  for (int j = 0; j < NW; ++j) w[j] = p[j];
+}
+
+// Shift-add hash state after the 64 bytes held in w[0..16), i.e. before the
+// thread's first window end: h = sum_j b[63-j] << (S*j) mod 2^32 (bytes older
+// than 32/S positions have shifted out).  For S = 2 and S = 1 four bytes at a
+// time with one dot product each: the weights 4^3..4^0 (or 2^3..2^0) of a
+// word's bytes fit in bytes.
+template <int S>
+__device__ __forceinline__ uint32_t screen_init(const uint32_t *w) {
+  if constexpr (S == 2) {
+    uint32_t h = 0;
+#pragma unroll
+    for (int q = 12; q < 16; ++q) h = __builtin_amdgcn_udot4(w[q], 0x01041040u, h << 8, false);
+    return h;
+  } else if constexpr (S == 1) {
+    uint32_t h = 0;
+#pragma unroll
+    for (int q = 8; q < 16; ++q) h = __builtin_amdgcn_udot4(w[q], 0x01020408u, h << 4, false);
+    return h;
+  } else {
+    constexpr int WU = 32 / S - 1;  // bytes before the first window end that are still in the hash
+    uint32_t h = 0;
+#pragma unroll
+    for (int j = 64 - WU; j < 64; ++j) h = (h << S) + byte_at(w, j);
+    return h;
+  }
 }
 
 // OR of the wave ballots, kept as a sequential chain of scalar ORs (a
@@ -135,12 +164,9 @@ __device__ __forceinline__ void any_or(uint64_t &any, uint64_t b) {
 template <int C, int S, int NT, bool ANY>
 __device__ __forceinline__ void pass_list_screen(const uint32_t *tw, uint32_t msk, const uint32_t *tg, uint64_t &any,
                                                  Bits<C> &bits) {
-  constexpr int WU = 32 / S - 1;  // bytes needed before the first window end
   uint32_t w[16 + C / 4];
   load_words<16 + C / 4>(w, tw);
-  uint32_t h = 0, acc = 0;
-#pragma unroll
-  for (int j = 64 - WU; j < 64; ++j) h = (h << S) + byte_at(w, j);
+  uint32_t h = screen_init<S>(w), acc = 0;
   if (RK_MIN_ACC && ANY && NT == 1) {
     // one target: the minimum of h ^ target over the windows is zero iff
     // some window matches; no per-window scalar work
@@ -174,22 +200,24 @@ __device__ __forceinline__ void pass_list_screen(const uint32_t *tw, uint32_t ms
   }
 }
 
+// Set test against a cuckoo table in LDS: the key is in one of its two slots.
+__device__ __forceinline__ bool in_cuckoo(const uint32_t *tab, uint32_t sh, uint32_t h) {
+  return (tab[ck_slot1(h, sh)] == h) | (tab[ck_slot2(h, sh)] == h);
+}
+
 template <int C, int S, bool ANY>
-__device__ __forceinline__ void pass_table_screen(const uint32_t *tw, const uint32_t *fp, uint32_t fmask, uint64_t &any,
-                                                  Bits<C> &bits) {
-  constexpr int WU = 32 / S - 1;
+__device__ __forceinline__ void pass_table_screen(const uint32_t *tw, uint32_t msk, const uint32_t *tab, uint32_t sh,
+                                                  uint64_t &any, Bits<C> &bits) {
   uint32_t w[16 + C / 4];
   load_words<16 + C / 4>(w, tw);
-  uint32_t h = 0, acc = 0;
-#pragma unroll
-  for (int j = 64 - WU; j < 64; ++j) h = (h << S) + byte_at(w, j);
+  uint32_t h = screen_init<S>(w), acc = 0;
 #pragma unroll
   for (int i = 0; i < C; ++i) {
     h = (h << S) + byte_at(w, 64 + i);
-    const uint32_t e = fp[h & fmask];
-    const uint32_t f = h >> 16;
-    if (ANY) any_or(any, ballot((e & 0xFFFFu) == f) | ballot((e >> 16) == f));
-    else put_bit<C>(bits, acc, i, ((e & 0xFFFFu) == f) || ((e >> 16) == f));
+    const uint32_t v = (S == 8) ? (h & msk) : h;
+    const bool c = in_cuckoo(tab, sh, v);
+    if (ANY) any_or(any, ballot(c));
+    else put_bit<C>(bits, acc, i, c);
   }
 }
 
@@ -254,7 +282,7 @@ __device__ __forceinline__ OutStream out_stream(const uint8_t *mine, uint32_t m)
 
 template <int C, bool ANY, bool TABLE, int NT, int OUTK>
 __device__ __forceinline__ void pass_exact(const uint32_t *tw, OutStream os, uint32_t m, uint32_t r, const uint32_t *tg,
-                                           const uint32_t *fp, uint32_t fmask, uint64_t &any, Bits<C> &bits) {
+                                           const uint32_t *fp, uint32_t sh, uint64_t &any, Bits<C> &bits) {
   uint32_t w[16 + C / 4];
   load_words<16 + C / 4>(w, tw);
   uint64_t s = exact_init(w, m);
@@ -268,11 +296,9 @@ __device__ __forceinline__ void pass_exact(const uint32_t *tw, OutStream os, uin
     }
     s = exact_step_k<OUTK>(s, byte_at(w, 64 + i), (ow >> (8 * (i & 3))) & 0xFFu, r);
     if (TABLE) {
-      const uint32_t h = (uint32_t)canon(s);
-      const uint32_t e = fp[h & fmask];
-      const uint32_t f = h >> 16;
-      if (ANY) any_or(any, ballot((e & 0xFFFFu) == f) | ballot((e >> 16) == f));
-      else put_bit<C>(bits, acc, i, ((e & 0xFFFFu) == f) || ((e >> 16) == f));
+      const bool c = in_cuckoo(fp, sh, (uint32_t)canon(s));
+      if (ANY) any_or(any, ballot(c));
+      else put_bit<C>(bits, acc, i, c);
     } else {
       // lazy state s = H + j*q for j in {0,1,2}; the host lists the low words
       const uint32_t lo = (uint32_t)s;
@@ -291,11 +317,11 @@ __device__ __forceinline__ void pass_exact(const uint32_t *tw, OutStream os, uin
 
 template <int C, bool ANY, bool TABLE, int NT>
 __device__ __forceinline__ void pass_exact_r(const uint32_t *tw, OutStream os, uint32_t m, uint32_t r, const uint32_t *tg,
-                                             const uint32_t *fp, uint32_t fmask, uint64_t &any, Bits<C> &bits) {
+                                             const uint32_t *fp, uint32_t sh, uint64_t &any, Bits<C> &bits) {
   const int k = out_kind(r);
-  if (k == 0) pass_exact<C, ANY, TABLE, NT, 0>(tw, os, m, r, tg, fp, fmask, any, bits);
-  else if (k == 1) pass_exact<C, ANY, TABLE, NT, 1>(tw, os, m, r, tg, fp, fmask, any, bits);
-  else pass_exact<C, ANY, TABLE, NT, 2>(tw, os, m, r, tg, fp, fmask, any, bits);
+  if (k == 0) pass_exact<C, ANY, TABLE, NT, 0>(tw, os, m, r, tg, fp, sh, any, bits);
+  else if (k == 1) pass_exact<C, ANY, TABLE, NT, 1>(tw, os, m, r, tg, fp, sh, any, bits);
+  else pass_exact<C, ANY, TABLE, NT, 2>(tw, os, m, r, tg, fp, sh, any, bits);
 }
 
 // kDump: canonical rolling hash of windows x = e - m + 1 with x % stride == 0.
@@ -357,10 +383,10 @@ __device__ __forceinline__ void run_pass(const BucketDesc &D, const uint32_t *tw
         else pass_list_screen<C, 8, 4, ANY>(tw, D.mask, D.tgt, any, bits);
       }
     } else {
-      if (sh == 1) pass_table_screen<C, 1, ANY>(tw, fp, D.fp_mask, any, bits);
-      else if (sh == 2) pass_table_screen<C, 2, ANY>(tw, fp, D.fp_mask, any, bits);
-      else if (sh == 4) pass_table_screen<C, 4, ANY>(tw, fp, D.fp_mask, any, bits);
-      else pass_table_screen<C, 8, ANY>(tw, fp, D.fp_mask, any, bits);
+      if (sh == 1) pass_table_screen<C, 1, ANY>(tw, D.mask, fp, D.fp_mask, any, bits);
+      else if (sh == 2) pass_table_screen<C, 2, ANY>(tw, D.mask, fp, D.fp_mask, any, bits);
+      else if (sh == 4) pass_table_screen<C, 4, ANY>(tw, D.mask, fp, D.fp_mask, any, bits);
+      else pass_table_screen<C, 8, ANY>(tw, D.mask, fp, D.fp_mask, any, bits);
     }
   } else {
     if (D.kind == kListExact) {
@@ -383,9 +409,9 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *wsum, 
     const uint32_t y = __shfl_up(x, d, 64);
     if (lane >= (uint32_t)d) x += y;
   }
-  __syncthreads();
+  wg_barrier();
   if (lane == 63) wsum[wave] = x;
-  __syncthreads();
+  wg_barrier();
   uint32_t before = 0, tot = 0;
 #pragma unroll
   for (int i = 0; i < NW; ++i) {
@@ -413,10 +439,11 @@ __device__ __forceinline__ uint32_t screen_key(const uint8_t *end, uint32_t shif
   return h & mask;
 }
 
-// Run of entries (first | count << 16) stored under key, or kNoLink.
-__device__ __forceinline__ uint32_t key_lookup(const uint8_t *img, const BucketDesc &D, uint64_t key) {
-  const uint64_t *keys = (const uint64_t *)(img + D.ht_off);
-  const uint32_t *runs = (const uint32_t *)(img + D.ht_off + 8u * (D.ht_mask + 1u));
+// Run of entries (first | count << 16) stored under key, or kNoLink.  The key
+// table is read from the instance image in device memory (gimg).
+__device__ __forceinline__ uint32_t key_lookup(const uint8_t *gimg, const BucketDesc &D, uint64_t key) {
+  const uint64_t *keys = (const uint64_t *)(gimg + D.ht_off);
+  const uint32_t *runs = (const uint32_t *)(gimg + D.ht_off + 8u * (D.ht_mask + 1u));
   uint32_t slot = ht_slot(key, D.ht_mask);
   for (uint32_t probe = 0; probe <= D.ht_mask; ++probe) {
     const uint64_t k = keys[slot];
@@ -427,37 +454,88 @@ __device__ __forceinline__ uint32_t key_lookup(const uint8_t *img, const BucketD
   return kNoLink;
 }
 
-__device__ __forceinline__ bool bytes_equal(const uint8_t *a, const uint8_t *b, uint32_t m) {
-  for (uint32_t j = 0; j < m; ++j)
-    if (a[j] != b[j]) return false;
+// Compares the m bytes ending at *end (LDS tile, any alignment) with the
+// pattern at pat (device memory, 4-byte aligned), four bytes per step: the tile
+// dwords are realigned with alignbyte and the tail of the last one is masked.
+__device__ __forceinline__ bool window_equals(const uint8_t *end, const uint8_t *pat, uint32_t m) {
+  const uint8_t *a = end - (m - 1);
+  const uint32_t mis = (uint32_t)(uintptr_t)a & 3u;
+  const uint32_t *aw = (const uint32_t *)(a - mis);
+  const uint32_t *pw = (const uint32_t *)pat;
+  uint32_t lo = aw[0];
+  for (uint32_t q = 0; 4 * q < m; ++q) {
+    const uint32_t hi = aw[q + 1];
+    const uint32_t rem = m - 4 * q;
+    const uint32_t keep = rem >= 4 ? 0xFFFFFFFFu : ((1u << (8 * rem)) - 1u);
+    if ((__builtin_amdgcn_alignbyte(hi, lo, mis) ^ pw[q]) & keep) return false;
+    lo = hi;
+  }
   return true;
 }
 
-// Walks the run of entries found for the candidate window ending at *end
-// (global end index e) and calls hit(entry) for every pattern that occurs
-// there: the window of the entry's length must start inside the text, have
-// the entry's exact hash and equal bytes.  Entries of a run are sorted by
-// length, so one backward pass accumulates the exact hash of every suffix:
-// S_m = sum_{j<m} T[e-j] * 256^j = hash of the m-byte window ending at e.
-template <typename F>
-__device__ __forceinline__ void verify_run(const uint8_t *img, const BucketDesc &D, uint32_t run, const uint8_t *end,
-                                           int64_t e, F &&hit) {
-  if (run == kNoLink) return;
-  const Entry *ent = (const Entry *)(img + D.ent_off);
+// Verifies the run of entries found for the candidate window ending at *end
+// (global end index e): an entry matches when its window starts inside the
+// text and its bytes equal the window's (the byte comparison of Sec. 3.1 that
+// follows every hash hit).  Consecutive entries with the same pattern bytes
+// (identical patterns under several ids) share one comparison.  Returns the
+// number of matching entries; bit i of mask is set for a matching entry i < 32
+// of the run.
+__device__ __forceinline__ uint32_t verify_run(const uint8_t *gimg, const BucketDesc &D, uint32_t run, const uint8_t *end,
+                                               int64_t e, uint32_t &mask) {
+  mask = 0;
+  if (run == kNoLink) return 0;
+  const Entry *ent = (const Entry *)(gimg + D.ent_off);
   const uint32_t first = run & 0xFFFFu, cnt = run >> 16;
-  uint64_t S = 0;   // lazy: < 2^62
-  uint32_t j = 0;   // bytes accumulated
-  uint32_t r = 0;   // 8j mod 61
-  for (uint32_t t = first; t < first + cnt; ++t) {
-    const uint32_t m = ent[t].off_m >> 24;
-    if (e - (int64_t)m + 1 < 0) continue;  // window would start before the text
-    for (; j < m; ++j) {
-      S += rot61((uint64_t)end[-(int)j], r);
-      S = (S & kQ) + (S >> 61);
-      r = (r + 8u >= 61u) ? r + 8u - 61u : r + 8u;
+  uint32_t nh = 0, prev = kNoLink;
+  bool prev_ok = false;
+  for (uint32_t i = 0; i < cnt; ++i) {
+    const uint32_t om = ent[first + i].off_m;
+    if (om != prev) {
+      const uint32_t m = om >> 24;
+      prev_ok = e - (int64_t)m + 1 >= 0 && window_equals(end, gimg + D.pat_off + (om & 0xFFFFFFu), m);
+      prev = om;
     }
-    if (canon(S) != ent[t].hx) continue;
-    if (bytes_equal(end - (m - 1), img + D.pat_off + (ent[t].off_m & 0xFFFFFFu), m)) hit(ent[t]);
+    if (prev_ok) {
+      ++nh;
+      if (i < 32) mask |= 1u << i;
+    }
+  }
+  return nh;
+}
+
+// Entry i of a run matched?  From the mask for i < 32, else compared again.
+__device__ __forceinline__ bool entry_hit(const uint8_t *gimg, const BucketDesc &D, const Entry &en, uint32_t i,
+                                          uint32_t mask, const uint8_t *end, int64_t e) {
+  if (i < 32) return (mask >> i) & 1u;
+  const uint32_t m = en.off_m >> 24;
+  return e - (int64_t)m + 1 >= 0 && window_equals(end, gimg + D.pat_off + (en.off_m & 0xFFFFFFu), m);
+}
+
+// ------------------------------------------------------- tile staging (LDS DMA)
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+// Issues the loads of one tile into an LDS slot: text bytes [tstart - kFront,
+// tstart + W) as 16-byte chunks that the load unit writes straight into LDS
+// (no register staging, so the next tile's loads cost no VGPRs while they are
+// in flight).  The body is W/1024 whole-wave loads of 1 KiB (lane i: bytes
+// 16i..16i+15) dealt round-robin to the waves; the last wave also loads the
+// 64-byte front halo with four lanes.  Chunks outside the text read the
+// text's first chunk instead: those LDS bytes only feed windows that start
+// before the text or end after it, which the edge masks drop.
+template <int WG, int C>
+__device__ __forceinline__ void dma_tile(uint8_t *slot, const uint8_t *text, uint64_t n, int64_t tstart) {
+  constexpr uint32_t W = WG * C, J = W / 1024, NW = WG / 64;
+  static_assert(W % 1024 == 0, "a tile is a whole number of 1 KiB wave loads");
+  const uint32_t lane = threadIdx.x & 63, wave = uni(threadIdx.x >> 6);
+  for (uint32_t j = wave; j < J; j += NW) {
+    const uint64_t g = (uint64_t)tstart + 1024u * j + 16u * lane;
+    const uint8_t *src = g < n ? text + g : text;
+    __builtin_amdgcn_global_load_lds((const void *)src, (lds_void_t *)(slot + kFront + 1024u * j), 16, 0, 0);
+  }
+  if (wave == NW - 1 && lane < 4) {
+    const int64_t g = tstart - (int64_t)kFront + 16 * (int64_t)lane;
+    const uint8_t *src = g >= 0 ? text + g : text;
+    __builtin_amdgcn_global_load_lds((const void *)src, (lds_void_t *)slot, 16, 0, 0);
   }
 }
 
@@ -471,13 +549,10 @@ __global__ __launch_bounds__(WG, RK_WAVES) void scan_kernel(ScanParams p) {
 __global__ __launch_bounds__(WG) void scan_kernel(ScanParams p) {
 #endif
   constexpr uint32_t W = WG * C;
-  constexpr uint32_t TILE_LDS = (kFront + W + 16 + 15) & ~15u;
-  constexpr uint32_t NCH = (kFront + W) / 16;  // 16-byte chunks loaded per tile
-  constexpr uint32_t LOADS = (NCH + WG - 1) / WG;
+  constexpr uint32_t TILE_LDS = (kFront + W + 16 + 15) & ~15u;  // one slot
   constexpr int NB = (C + 31) / 32;
   extern __shared__ __align__(16) uint8_t lds[];
-  uint8_t *tile = lds;
-  uint32_t *cand = (uint32_t *)(lds + TILE_LDS);
+  uint32_t *cand = (uint32_t *)(lds + 2 * TILE_LDS);
   uint32_t *misc = cand + kCandCap;  // [0,16) scan sums, [16,48) any flags, [48] queue
   uint8_t *img = (uint8_t *)(misc + 64);
 
@@ -485,15 +560,16 @@ __global__ __launch_bounds__(WG) void scan_kernel(ScanParams p) {
   uint32_t cur_inst = kNoLink;
   uint64_t static_item = blockIdx.x;
   uint32_t flag_parity = 0;
+  uint32_t dense_mask = 0;  // buckets whose last tile had candidates
   const uint64_t nitems = p.nitems_dev ? min(p.nitems, (uint64_t)*p.nitems_dev) : p.nitems;
 
   // Next work item (uniform across the workgroup).  With a queue, thread 0
   // pops and the value is read back after the barrier that follows.
   auto pop = [&]() -> uint64_t {
     if (p.queue) {
-      __syncthreads();
+      wg_barrier();
       if (tid == 0) misc[48] = atomicAdd(p.queue, 1u);
-      __syncthreads();
+      wg_barrier();
       return misc[48];
     }
     const uint64_t it = static_item;
@@ -522,50 +598,46 @@ __global__ __launch_bounds__(WG) void scan_kernel(ScanParams p) {
     it.tstart = (int64_t)((it.gt - p.inst[lo].tile_base) * W);
     return it;
   };
-  // text bytes [tstart - kFront, tstart + W) in aligned 16-byte chunks
-  uint4 v[LOADS];
-  auto issue_loads = [&](const Item &it) {
-#pragma unroll
-    for (uint32_t u = 0; u < LOADS; ++u) {
-      const uint32_t q = tid + u * WG;
-      const int64_t g = it.tstart - (int64_t)kFront + 16 * (int64_t)q;
-      v[u] = make_uint4(0, 0, 0, 0);
-      if (q < NCH && g >= 0 && (uint64_t)g < it.n) v[u] = *(const uint4 *)(it.text + g);
-    }
-  };
-
+  // Two LDS slots: tile k is processed in one while the loads of tile k+1
+  // land in the other.
+  uint32_t slot = 0;
+  const uint8_t *gimg = nullptr;  // current instance image in device memory
   uint64_t item = pop();
   Item cur;
   if (item < nitems) {
     cur = locate(item);
-    if (RK_PREFETCH) issue_loads(cur);
+    dma_tile<WG, C>(lds, cur.text, cur.n, cur.tstart);
   }
   while (item < nitems) {
-    const uint64_t next = pop();  // ends with a barrier when a queue is used
-    if (!RK_PREFETCH) issue_loads(cur);
-    __syncthreads();  // previous tile finished with tile / cand / image
+    const uint64_t next = pop();
+    const bool have_next = next < nitems;
+    Item nx;
+    if (have_next) nx = locate(next);
+    // this tile has landed, and every wave is done with the other slot
+    wg_barrier_loads();
+    uint8_t *tile = lds + slot * TILE_LDS;
     if (cur.inst != cur_inst) {
-      const uint4 *src = (const uint4 *)(p.blob + p.inst[cur.inst].img_off);
+      // the image's leading part goes to LDS; the rest is read in place
+      gimg = p.blob + p.inst[cur.inst].img_off;
+      const uint4 *src = (const uint4 *)gimg;
       uint4 *dst = (uint4 *)img;
-      const uint32_t nq = p.inst[cur.inst].img_bytes / 16u;
+      const uint32_t nq = p.inst[cur.inst].lds_bytes / 16u;
       for (uint32_t q = tid; q < nq; q += WG) dst[q] = src[q];
       cur_inst = cur.inst;
-    }
-#pragma unroll
-    for (uint32_t u = 0; u < LOADS; ++u) {
-      const uint32_t q = tid + u * WG;
-      if (q < NCH) *(uint4 *)(tile + 16 * q) = v[u];
-    }
-    __syncthreads();
-    // the next tile's loads are in flight while this one is processed
-    Item nx;
-    if (next < nitems) {
-      nx = locate(next);
-      if (RK_PREFETCH) issue_loads(nx);
+      wg_barrier();
     }
     const uint64_t gt = cur.gt;
     const uint64_t n = cur.n;
     const int64_t tstart = cur.tstart;
+    uint64_t *slab = nullptr;
+    if (p.out) slab = p.direct ? (p.out + p.tile_offsets[gt]) : (p.out + gt * (uint64_t)p.slab_cap);
+    const uint32_t cap = p.direct ? 0xFFFFFFFFu : p.slab_cap;
+    // Everything this tile reads from memory into registers is there before
+    // the next tile's loads are issued (the compiler would otherwise wait for
+    // a late load with a count that also covers those loads).
+    __asm__ volatile("" ::"v"(slab), "v"(n), "v"(tstart), "v"(gt), "v"(gimg) : "memory");
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+    if (have_next) dma_tile<WG, C>(lds + (slot ^ 1u) * TILE_LDS, nx.text, nx.n, nx.tstart);
 
     // this thread's bytes: 64 before its first window end, then C
     const uint32_t *tw = (const uint32_t *)(tile + kFront + tid * C - 64);
@@ -575,9 +647,6 @@ __global__ __launch_bounds__(WG) void scan_kernel(ScanParams p) {
     const ImageHeader *H = (const ImageHeader *)img;
     const uint32_t nb = uni(H->nbuckets);
     uint32_t tile_hits = 0;
-    uint64_t *slab = nullptr;
-    if (p.out) slab = p.direct ? (p.out + p.tile_offsets[gt]) : (p.out + gt * (uint64_t)p.slab_cap);
-    const uint32_t cap = p.direct ? 0xFFFFFFFFu : p.slab_cap;
 
     for (uint32_t b = 0; b < nb; ++b) {
       const BucketDesc *dp = (const BucketDesc *)(img + sizeof(ImageHeader) + 64u * b);
@@ -608,18 +677,23 @@ __global__ __launch_bounds__(WG) void scan_kernel(ScanParams p) {
         }
       }
 
-      // ---- pass 1: wave-level "any candidate" over every window
-      uint64_t any = 0;
-      Bits<C> nob;
-      run_pass<C, true, FAM>(D, tw, os, r, fp, any, nob);
-      uint32_t *flags = misc + 16 + 16 * flag_parity;
-      flag_parity ^= 1u;
-      if (lane == 0) flags[wave] = any != 0;
-      __syncthreads();
-      uint32_t blk_any = 0;
+      // ---- pass 1: wave-level "any candidate" over every window.  Skipped
+      // while the bucket's previous tile had candidates (dense hits): the
+      // mask pass and its block scan decide then.
+      const bool dense = b < 32 && ((dense_mask >> b) & 1u);
+      if (!dense) {
+        uint64_t any = 0;
+        Bits<C> nob;
+        run_pass<C, true, FAM>(D, tw, os, r, fp, any, nob);
+        uint32_t *flags = misc + 16 + 16 * flag_parity;
+        flag_parity ^= 1u;
+        if (lane == 0) flags[wave] = any != 0;
+        wg_barrier();
+        uint32_t blk_any = 0;
 #pragma unroll
-      for (int i = 0; i < WG / 64; ++i) blk_any |= flags[i];
-      if (!blk_any) continue;
+        for (int i = 0; i < WG / 64; ++i) blk_any |= flags[i];
+        if (!blk_any) continue;
+      }
 
       // ---- pass 2 (only when some window of the tile passed): per-thread masks
       Bits<C> bits;
@@ -651,9 +725,10 @@ __global__ __launch_bounds__(WG) void scan_kernel(ScanParams p) {
       for (int j = 0; j < NB; ++j) cnt += __builtin_popcount(bits.b[j]);
       uint32_t ncand;
       const uint32_t cbase = block_excl_scan<WG>(cnt, misc, ncand);
+      if (b < 32) dense_mask = ncand ? (dense_mask | (1u << b)) : (dense_mask & ~(1u << b));
 
       for (uint32_t r0 = 0; r0 < ncand; r0 += kCandCap) {
-        __syncthreads();  // cand list free
+        wg_barrier();  // cand list free
         if (cnt) {
           uint32_t idx = cbase;
 #pragma unroll
@@ -668,11 +743,11 @@ __global__ __launch_bounds__(WG) void scan_kernel(ScanParams p) {
             }
           }
         }
-        __syncthreads();
+        wg_barrier();
         const uint32_t nc = min(kCandCap, ncand - r0);
         for (uint32_t i0 = 0; i0 < nc; i0 += WG) {
           const uint32_t ci = i0 + tid;
-          uint32_t run = kNoLink, nh = 0;
+          uint32_t run = kNoLink, nh = 0, hmask = 0;
           const uint8_t *end = nullptr;
           int64_t e = 0;
           const bool screen = D.kind == kListScreen || D.kind == kTableScreen;
@@ -682,18 +757,22 @@ __global__ __launch_bounds__(WG) void scan_kernel(ScanParams p) {
             e = tstart + (int64_t)e_rel;
             const uint64_t key = screen ? (uint64_t)screen_key(end, D.shift & 0xFFu, D.mask)
                                         : horner_exact(end - (m - 1), m);
-            run = key_lookup(img, D, key);
-            verify_run(img, D, run, end, e, [&](const Entry &) { ++nh; });
+            run = key_lookup(gimg, D, key);
+            nh = verify_run(gimg, D, run, end, e, hmask);
           }
           uint32_t nht;
           const uint32_t hb = block_excl_scan<WG>(nh, misc, nht);
           if (nh) {
             uint32_t o = tile_hits + hb;
-            verify_run(img, D, run, end, e, [&](const Entry &en) {
+            const Entry *ent = (const Entry *)(gimg + D.ent_off);
+            const uint32_t first = run & 0xFFFFu, cnt = run >> 16;
+            for (uint32_t i = 0; i < cnt; ++i) {
+              const Entry en = ent[first + i];
+              if (!entry_hit(gimg, D, en, i, hmask, end, e)) continue;
               const uint64_t x = (uint64_t)(e - (int64_t)(en.off_m >> 24) + 1);
               if (o < cap) slab[o] = ((uint64_t)en.pid << kPosBits) | x;
               ++o;
-            });
+            }
           }
           tile_hits += nht;
         }
@@ -710,6 +789,7 @@ __global__ __launch_bounds__(WG) void scan_kernel(ScanParams p) {
     }
     item = next;
     cur = nx;
+    slot ^= 1u;
   }
 }
 
@@ -977,7 +1057,7 @@ uint32_t scan_lds_bytes(int cfg, uint32_t img_cap) {
   const TileCfg c = kTileCfgs[cfg];
   const uint32_t W = c.wg * c.c;
   const uint32_t tile = (kFront + W + 16 + 15) & ~15u;
-  return tile + kCandCap * 4 + 64 * 4 + img_cap;
+  return 2 * tile + kCandCap * 4 + 64 * 4 + img_cap;  // two tile slots
 }
 
 hipError_t launch_scan(int cfg, int fam, const ScanParams &p, uint32_t grid, uint32_t lds_bytes, hipStream_t s) {
@@ -1111,24 +1191,3 @@ hipError_t launch_stream_read(const void *data, uint64_t n, uint32_t *out, uint3
 
 }  // namespace rk
 
-namespace rk {
-
-// ------------------------------------------------------- segmented copy
-// dst_k[0..len_k) = src[src_off_k .. src_off_k + len_k) for every segment;
-// the server uses it to give each request a contiguous copy of its patterns'
-// hit lists out of a merged step.  Segments are at most 65536 entries long.
-__global__ __launch_bounds__(256) void segment_copy_kernel(const uint64_t *src, const CopySeg *segs, uint32_t nseg) {
-  for (uint32_t s = blockIdx.x; s < nseg; s += gridDim.x) {
-    const CopySeg g = segs[s];
-    for (uint64_t i = threadIdx.x; i < g.len; i += 256) g.dst[i] = src[g.src_off + i];
-  }
-}
-
-hipError_t launch_segment_copy(const uint64_t *src, const CopySeg *segs, uint32_t nseg, hipStream_t s) {
-  if (nseg == 0) return hipSuccess;
-  const uint32_t grid = nseg < 4096 ? nseg : 4096;
-  hipLaunchKernelGGL(segment_copy_kernel, dim3(grid), dim3(256), 0, s, src, segs, nseg);
-  return hipGetLastError();
-}
-
-}  // namespace rk

@@ -80,7 +80,7 @@ rk_status plan_build_host(rk_ctx *ctx, const rk_instance *inst, uint32_t count, 
   P->fam = mode == RK_MODE_EXACT ? kFamExact : kFamScreen1;
   for (const VInst &v : P->vinsts)
     if (mode != RK_MODE_EXACT && !v.only_one_list) P->fam = kFamScreen;
-  for (const VInst &v : P->vinsts) P->img_cap = std::max(P->img_cap, v.img_bytes);
+  for (const VInst &v : P->vinsts) P->img_cap = std::max(P->img_cap, v.lds_bytes);
   P->img_cap = (uint32_t)align_up(P->img_cap, 16);
   if (batch) {
     const uint32_t W = kTileCfgs[P->cfg].wg * kTileCfgs[P->cfg].c;
@@ -94,7 +94,7 @@ rk_status plan_build_host(rk_ctx *ctx, const rk_instance *inst, uint32_t count, 
       d.tile_base = base;
       d.ntiles = (R.n + W - 1) / W;
       d.img_off = v.img_off;
-      d.img_bytes = v.img_bytes;
+      d.lds_bytes = v.lds_bytes;
       descs.push_back(d);
       base += d.ntiles;
     }
@@ -306,7 +306,7 @@ rk_status count_enqueue(rk_ctx *ctx, const rk_plan *plan, const uint8_t *text, u
       d[i].tile_base = L.T1 * i;
       d[i].ntiles = L.T1;
       d[i].img_off = plan->vinsts[i].img_off;
-      d[i].img_bytes = plan->vinsts[i].img_bytes;
+      d[i].lds_bytes = plan->vinsts[i].lds_bytes;
     }
     const size_t bytes = d.size() * sizeof(InstDesc);
     // hipMemcpyAsync from pageable memory stages the data before returning
@@ -494,7 +494,7 @@ extern "C" rk_status rk_scan_dump(rk_ctx *ctx, const uint8_t *text, uint64_t n, 
   // image: header + one kDump bucket; then the instance descriptor
   uint8_t host[256];
   memset(host, 0, sizeof host);
-  ImageHeader hd = {1u, 128u, m, 0u};
+  ImageHeader hd = {1u, 128u, m, 128u};
   BucketDesc d;
   memset(&d, 0, sizeof d);
   d.m = m;
@@ -509,7 +509,7 @@ extern "C" rk_status rk_scan_dump(rk_ctx *ctx, const uint8_t *text, uint64_t n, 
   I.tile_base = 0;
   I.ntiles = (n + W - 1) / W;
   I.img_off = 0;
-  I.img_bytes = 128;
+  I.lds_bytes = 128;
   memcpy(host + 128, &I, sizeof I);
   hipError_t e;
   if (!ctx->dump_dev) {

@@ -12,6 +12,7 @@
 #include <map>
 #include <new>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/rk.h"
@@ -115,38 +116,77 @@ static uint32_t group_id(int mode, uint32_t m) {
   return 100 + screen_shift(m);
 }
 
-static bool build_fp_table(const std::vector<uint32_t> &keys, uint32_t bits, std::vector<uint32_t> &tab) {
-  const uint32_t S = 1u << bits;
-  tab.assign(S, 0);
-  std::vector<uint8_t> cnt(S, 0);
-  for (uint32_t h : keys) {
-    const uint32_t slot = h & (S - 1);
-    const uint32_t f = h >> 16;
-    if (cnt[slot] == 0) {
-      tab[slot] = f | (f << 16);
-      cnt[slot] = 1;
-    } else if (cnt[slot] == 1) {
-      if ((tab[slot] & 0xFFFFu) == f) continue;
-      tab[slot] = (tab[slot] & 0xFFFFu) | (f << 16);
-      cnt[slot] = 2;
-    } else {
-      if ((tab[slot] & 0xFFFFu) == f || (tab[slot] >> 16) == f) continue;
-      return false;
+// Cuckoo table of 32-bit keys for the per-window set test: a key sits in one
+// of its two slots (ck_slot1 / ck_slot2, which the kernel computes the same
+// way), so a window costs two LDS reads and two full 32-bit compares and has
+// no false positives beyond hash equality.  Empty slots hold a value that is
+// no key.  At most 45% of the slots are used.
+static bool build_cuckoo(const std::vector<uint32_t> &keys, uint32_t bits, std::vector<uint32_t> &tab) {
+  const uint32_t S = 1u << bits, sh = 32 - bits;
+  std::vector<uint32_t> sorted(keys);
+  std::sort(sorted.begin(), sorted.end());
+  uint32_t filler = 0;
+  for (uint32_t k : sorted) {
+    if (k == filler) ++filler;
+    else if (k > filler) break;
+  }
+  tab.assign(S, filler);
+  std::vector<uint8_t> used(S, 0);
+  uint32_t rng = 0x2545F491u;
+  for (uint32_t key : keys) {
+    uint32_t cur = key;
+    bool placed = false;
+    for (int kick = 0; kick < 1000 && !placed; ++kick) {
+      const uint32_t a = ck_slot1(cur, sh), b = ck_slot2(cur, sh);
+      if (!used[a]) {
+        tab[a] = cur;
+        used[a] = 1;
+        placed = true;
+      } else if (!used[b]) {
+        tab[b] = cur;
+        used[b] = 1;
+        placed = true;
+      } else {
+        rng = rng * 1103515245u + 12345u;
+        const uint32_t v = ((rng >> 16) & 1u) ? a : b;
+        std::swap(cur, tab[v]);  // the evicted key tries its other slot next
+      }
     }
+    if (!placed) return false;
   }
   return true;
 }
 
-// Serialises one group into body (offsets relative to the body start) and
-// fills its descriptor.  Returns false if its keys do not fit a fingerprint
-// table of at most 2^13 slots (the caller then splits the group).
-static bool emit_group(const GroupIn &G, int mode, std::vector<uint8_t> &body, BucketDesc &D) {
+// A group serialised in two parts: what the kernel probes for every window
+// (the cuckoo table, staged in LDS) and what it walks for candidates only
+// (key table, entries, pattern bytes; read from the plan in device memory).
+// Offsets in the descriptor are relative to the start of each part.
+struct GroupBody {
+  std::vector<uint8_t> lds, glob;
+  BucketDesc D;
+};
+
+static uint32_t put_bytes(std::vector<uint8_t> &body, const void *p, size_t bytes) {
+  const uint32_t off = (uint32_t)align_up(body.size(), 16);
+  body.resize(off + align_up(bytes, 16), 0);
+  if (bytes) memcpy(body.data() + off, p, bytes);
+  return off;
+}
+
+// Serialises one group.  Returns false if its keys do not fit a cuckoo table
+// of at most 2^kMaxTableBits slots or it has more entries than a run can
+// address (the caller then splits the group).
+static bool emit_group(const GroupIn &G, GroupBody &out) {
   std::vector<PatRef> P = G.pats;
   std::stable_sort(P.begin(), P.end(), [](const PatRef &a, const PatRef &b) {
     if (a.key != b.key) return a.key < b.key;
     if (a.m != b.m) return a.m < b.m;
+    const int c = memcmp(a.p, b.p, a.m);  // identical patterns side by side
+    if (c) return c < 0;
     return a.pid < b.pid;
   });
+  if (P.size() > 0xFFFFu) return false;
+  BucketDesc &D = out.D;
   memset(&D, 0, sizeof D);
   D.m = G.m;
   D.npat = (uint32_t)P.size();
@@ -154,7 +194,7 @@ static bool emit_group(const GroupIn &G, int mode, std::vector<uint8_t> &body, B
   std::vector<uint64_t> dist;
   for (const PatRef &r : P)
     if (dist.empty() || dist.back() != r.key) dist.push_back(r.key);
-  std::vector<uint32_t> fpkeys;
+  std::vector<uint32_t> tkeys;
   if (!G.screen) {
     std::vector<uint32_t> lazy;
     for (uint64_t H : dist) {
@@ -168,7 +208,7 @@ static bool emit_group(const GroupIn &G, int mode, std::vector<uint8_t> &body, B
       D.shift = (uint32_t)(lazy.size() <= 2 ? 2u : 4u) << 8;  // compare count the kernel unrolls
     } else {
       D.kind = kTableExact;
-      for (uint64_t H : dist) fpkeys.push_back((uint32_t)H);
+      for (uint64_t H : dist) tkeys.push_back((uint32_t)H);  // low word of the canonical hash
     }
   } else {
     D.shift = G.shift;
@@ -178,26 +218,21 @@ static bool emit_group(const GroupIn &G, int mode, std::vector<uint8_t> &body, B
       D.shift |= (dist.size() == 1 ? 1u : 4u) << 8;  // compare count the kernel unrolls
     } else {
       D.kind = kTableScreen;
-      for (uint64_t h : dist) fpkeys.push_back((uint32_t)h);
+      for (uint64_t h : dist) tkeys.push_back((uint32_t)h);
     }
   }
-  auto put = [&body](const void *p, size_t bytes) -> uint32_t {
-    const uint32_t off = (uint32_t)align_up(body.size(), 16);
-    body.resize(off + align_up(bytes, 16), 0);
-    if (bytes) memcpy(body.data() + off, p, bytes);
-    return off;
-  };
   if (D.kind == kTableScreen || D.kind == kTableExact) {
+    std::sort(tkeys.begin(), tkeys.end());
+    tkeys.erase(std::unique(tkeys.begin(), tkeys.end()), tkeys.end());
     uint32_t bits = 6;
-    while ((1u << bits) < fpkeys.size()) ++bits;
-    ++bits;  // load factor <= 1/2 before the two-way slots
-    std::vector<uint32_t> fptab;
+    while ((1u << bits) * 9u < tkeys.size() * 20u) ++bits;  // load <= 45%
+    std::vector<uint32_t> tab;
     bool ok = false;
-    for (; bits <= 13; ++bits)
-      if ((ok = build_fp_table(fpkeys, bits, fptab))) break;
+    for (; bits <= kMaxTableBits; ++bits)
+      if ((ok = build_cuckoo(tkeys, bits, tab))) break;
     if (!ok) return false;
-    D.fp_mask = (1u << bits) - 1;
-    D.fp_off = put(fptab.data(), fptab.size() * 4);
+    D.fp_mask = 32 - bits;  // the kernel's slot shift
+    D.fp_off = put_bytes(out.lds, tab.data(), tab.size() * 4);
   }
   // key -> run of entries (first | count << 16), open addressing
   const uint32_t S = std::max<uint32_t>(2, next_pow2(2 * (uint32_t)dist.size()));
@@ -214,77 +249,97 @@ static bool emit_group(const GroupIn &G, int mode, std::vector<uint8_t> &body, B
     vals[s] = (uint32_t)i | ((uint32_t)(j - i) << 16);
     i = j;
   }
+  // pattern bytes, each at a 4-byte aligned offset (the kernel compares
+  // dwords); identical patterns under several ids are stored once
   uint32_t max_m = 0;
+  std::unordered_map<std::string, uint32_t> stored;
   for (size_t i = 0; i < P.size(); ++i) {
     ents[i].hx = P[i].hx;
     ents[i].pid = P[i].pid;
-    ents[i].off_m = (uint32_t)pb.size() | (P[i].m << 24);  // offset relative to the pattern block
-    pb.insert(pb.end(), P[i].p, P[i].p + P[i].m);
+    std::string s((const char *)P[i].p, P[i].m);
+    auto it = stored.find(s);
+    uint32_t off;
+    if (it != stored.end()) {
+      off = it->second;
+    } else {
+      off = (uint32_t)pb.size();
+      stored.emplace(std::move(s), off);
+      pb.insert(pb.end(), P[i].p, P[i].p + P[i].m);
+      pb.resize(align_up(pb.size(), 4), 0);
+    }
+    ents[i].off_m = off | (P[i].m << 24);  // offset relative to the pattern block
     max_m = std::max(max_m, P[i].m);
   }
   std::vector<uint8_t> ht(S * 12);
   memcpy(ht.data(), keys.data(), S * 8);
   memcpy(ht.data() + S * 8, vals.data(), S * 4);
   D.ht_mask = S - 1;
-  D.ht_off = put(ht.data(), ht.size());
-  D.ent_off = put(ents.data(), ents.size() * sizeof(Entry));
-  D.pat_off = put(pb.data(), pb.size());
+  D.ht_off = put_bytes(out.glob, ht.data(), ht.size());
+  D.ent_off = put_bytes(out.glob, ents.data(), ents.size() * sizeof(Entry));
+  D.pat_off = put_bytes(out.glob, pb.data(), pb.size());
   D.max_m = max_m;
   return true;
 }
 
-// Emits G, splitting its pattern list in halves while a fingerprint table
-// cannot hold it.
-static void expand_group(const GroupIn &G, int mode, std::vector<std::vector<uint8_t>> &bodies,
-                         std::vector<BucketDesc> &descs) {
-  std::vector<uint8_t> body;
-  BucketDesc D;
-  if (emit_group(G, mode, body, D) || G.pats.size() < 2) {
-    bodies.push_back(body);
-    descs.push_back(D);
+// Emits G, splitting its pattern list in halves while it does not fit.
+static void expand_group(const GroupIn &G, std::vector<GroupBody> &bodies) {
+  GroupBody gb;
+  if (emit_group(G, gb) || G.pats.size() < 2) {
+    bodies.push_back(std::move(gb));
     return;
   }
   GroupIn a = G, b = G;
   const size_t h = G.pats.size() / 2;
   a.pats.assign(G.pats.begin(), G.pats.begin() + h);
   b.pats.assign(G.pats.begin() + h, G.pats.end());
-  expand_group(a, mode, bodies, descs);
-  expand_group(b, mode, bodies, descs);
+  expand_group(a, bodies);
+  expand_group(b, bodies);
 }
 
-// Packs groups greedily into virtual instances whose image fits kImgLimit.
+// Packs groups greedily into virtual instances whose LDS part (header,
+// descriptors, cuckoo tables) fits kImgLimit.  Image layout:
+//   [ImageHeader][BucketDesc x nb][LDS parts ...][device-memory parts ...]
 static rk_status build_images(rk_ctx *ctx, const std::vector<GroupIn> &groups, int mode, uint32_t src_inst,
                               std::vector<VInst> &vinsts, std::vector<uint8_t> &blob) {
-  std::vector<std::vector<uint8_t>> bodies;
-  std::vector<BucketDesc> descs;
-  for (const GroupIn &G : groups) expand_group(G, mode, bodies, descs);
+  (void)mode;
+  std::vector<GroupBody> bodies;
+  for (const GroupIn &G : groups) expand_group(G, bodies);
   size_t i = 0;
   while (i < bodies.size()) {
     size_t j = i;
-    uint64_t body = 0;
+    uint64_t lds = 0;
     while (j < bodies.size()) {
       const uint64_t hdr = sizeof(ImageHeader) + 64 * (j - i + 1);
-      const uint64_t add = align_up(bodies[j].size(), 16);
-      if (j > i && hdr + body + add > kImgLimit) break;
-      body += add;
+      const uint64_t add = align_up(bodies[j].lds.size(), 16);
+      if (j > i && hdr + lds + add > kImgLimit) break;
+      lds += add;
       ++j;
     }
     const uint32_t hdr = (uint32_t)(sizeof(ImageHeader) + 64 * (j - i));
-    if (hdr + body > kImgLimit)
+    if (hdr + lds > kImgLimit)
       return set_err(ctx, RK_EUNSUPPORTED, "pattern group needs %llu bytes of LDS image (limit %u)",
-                     (unsigned long long)(hdr + body), kImgLimit);
+                     (unsigned long long)(hdr + lds), kImgLimit);
     std::vector<uint8_t> img(hdr, 0);
+    std::vector<uint32_t> lds_base(j - i), glob_base(j - i);
+    for (size_t b = i; b < j; ++b) {
+      lds_base[b - i] = (uint32_t)img.size();
+      img.insert(img.end(), bodies[b].lds.begin(), bodies[b].lds.end());
+      img.resize(align_up(img.size(), 16), 0);
+    }
+    const uint32_t lds_bytes = (uint32_t)img.size();
+    for (size_t b = i; b < j; ++b) {
+      glob_base[b - i] = (uint32_t)img.size();
+      img.insert(img.end(), bodies[b].glob.begin(), bodies[b].glob.end());
+      img.resize(align_up(img.size(), 16), 0);
+    }
     uint32_t max_m = 0;
     bool only_one_list = true;
     for (size_t b = i; b < j; ++b) {
-      const uint32_t base = (uint32_t)img.size();
-      img.insert(img.end(), bodies[b].begin(), bodies[b].end());
-      img.resize(align_up(img.size(), 16), 0);
-      BucketDesc d = descs[b];
-      if (d.kind == kTableScreen || d.kind == kTableExact) d.fp_off += base;
-      d.ht_off += base;
-      d.ent_off += base;
-      d.pat_off += base;
+      BucketDesc d = bodies[b].D;
+      if (d.kind == kTableScreen || d.kind == kTableExact) d.fp_off += lds_base[b - i];
+      d.ht_off += glob_base[b - i];
+      d.ent_off += glob_base[b - i];
+      d.pat_off += glob_base[b - i];
       max_m = std::max(max_m, d.max_m);
       if (d.kind != kListScreen || (d.shift >> 8) != 1u) only_one_list = false;
       memcpy(img.data() + sizeof(ImageHeader) + 64 * (b - i), &d, 64);
@@ -293,13 +348,14 @@ static rk_status build_images(rk_ctx *ctx, const std::vector<GroupIn> &groups, i
     hd.nbuckets = (uint32_t)(j - i);
     hd.bytes = (uint32_t)align_up(img.size(), 16);
     hd.max_m = max_m;
-    hd.pad = 0;
+    hd.lds_bytes = lds_bytes;
     img.resize(hd.bytes, 0);
     memcpy(img.data(), &hd, sizeof hd);
     VInst v;
     v.src = src_inst;
     v.img_off = (uint32_t)align_up(blob.size(), 256);
     v.img_bytes = hd.bytes;
+    v.lds_bytes = lds_bytes;
     v.nbuckets = hd.nbuckets;
     v.max_m = max_m;
     v.only_one_list = only_one_list;

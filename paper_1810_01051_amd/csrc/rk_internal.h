@@ -21,9 +21,9 @@ constexpr uint64_t kEmptyKey = ~0ull;      // empty exact-table slot (no canonic
 // Screen/test variants of one bucket (one pattern length inside one instance).
 enum BucketKind : uint32_t {
   kListScreen = 0,   // screen mode: shift-add hash compared with up to 4 targets
-  kTableScreen = 1,  // screen mode: shift-add hash probed in the LDS fingerprint table
+  kTableScreen = 1,  // screen mode: shift-add hash probed in the LDS cuckoo table
   kListExact = 2,    // exact mode: lazy 61-bit state compared with up to 4 lazy targets
-  kTableExact = 3,   // exact mode: canonical 61-bit hash probed in the fingerprint table
+  kTableExact = 3,   // exact mode: low word of the canonical 61-bit hash probed in the cuckoo table
   kDump = 4,         // exact rolling state written out for sampled windows (no patterns)
 };
 
@@ -36,8 +36,8 @@ struct BucketDesc {
   uint32_t shift;      // screen groups: shift s in bits 0-7, list target count (1 or 4) in bits 8-15
   uint32_t mask;       // screen-hash mask (all ones unless m < 4 with s = 8)
   uint32_t tgt[4];     // list kinds: targets (padded by repetition)
-  uint32_t fp_off;     // table kinds: byte offset of the fingerprint table (u32 slots)
-  uint32_t fp_mask;    // fingerprint slots - 1
+  uint32_t fp_off;     // table kinds: image offset of the cuckoo table (u32 keys; LDS part)
+  uint32_t fp_mask;    // table kinds: 32 - log2(table slots), the slot shift of ck_slot1/2
   uint32_t ht_off;     // key table: u64 keys[ht_mask+1], then u32 runs[ht_mask+1] (first | count << 16)
   uint32_t ht_mask;    // key-table slots - 1
   uint32_t ent_off;    // Entry[npat], sorted by (key, length, pattern id)
@@ -60,12 +60,20 @@ __host__ __device__ inline uint32_t ht_slot(uint64_t key, uint32_t mask) {
   return (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> 40) & mask;
 }
 
-// Header at the start of an instance image (16 bytes), followed by nb descriptors.
+// Two slots of a 32-bit key in a cuckoo table of 2^(32-sh) slots (built on
+// the host, probed by the kernel): multiplicative mixes of the key's low and
+// high 24 bits (each a 24 x 24-bit product, one full-rate multiply on gfx950).
+__host__ __device__ inline uint32_t ck_slot1(uint32_t h, uint32_t sh) { return ((h & 0xFFFFFFu) * 0x9E3779u) >> sh; }
+__host__ __device__ inline uint32_t ck_slot2(uint32_t h, uint32_t sh) { return ((h >> 8) * 0xC2B2AFu) >> sh; }
+constexpr uint32_t kMaxTableBits = 13;  // largest cuckoo table: 8192 slots, 32 KiB of LDS
+
+// Header at the start of an instance image (16 bytes), followed by nb
+// descriptors, the parts staged in LDS and the parts read from device memory.
 struct ImageHeader {
   uint32_t nbuckets;
   uint32_t bytes;      // total image bytes (multiple of 16)
   uint32_t max_m;
-  uint32_t pad;
+  uint32_t lds_bytes;  // leading bytes staged in LDS (header, descriptors, cuckoo tables)
 };
 
 // One instance of a scan job (48 bytes).
@@ -75,7 +83,7 @@ struct InstDesc {
   uint64_t tile_base;  // global id of this instance's tile 0
   uint64_t ntiles;
   uint32_t img_off;    // byte offset of the instance image in the plan blob (16-aligned)
-  uint32_t img_bytes;
+  uint32_t lds_bytes;  // leading image bytes the scan stages in LDS
   uint64_t pad;
 };
 static_assert(sizeof(InstDesc) == 48, "instance descriptor is 48 bytes");
@@ -102,13 +110,6 @@ struct ScanParams {
   uint64_t *dump_out;         // kDump buckets: destination of sampled hashes
   uint64_t dump_stride;
   uint64_t dump_cap;
-};
-
-// One segment of the server's per-request copy of a merged step's hits.
-struct CopySeg {
-  uint64_t src_off;  // first entry in the merged positions
-  uint64_t *dst;     // destination (device)
-  uint64_t len;      // entries
 };
 
 // Host-side geometry table (workgroup size, windows per thread).

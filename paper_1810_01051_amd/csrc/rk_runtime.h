@@ -30,6 +30,7 @@ struct VInst {
   uint32_t src;       // real instance index
   uint32_t img_off;   // in the plan blob
   uint32_t img_bytes;
+  uint32_t lds_bytes;  // leading bytes staged in LDS
   uint32_t nbuckets = 0;
   uint32_t max_m = 0;
   bool only_one_list = true;  // every bucket is a list screen with one target
@@ -120,7 +121,6 @@ void plan_sizes(const std::vector<uint8_t> &blob, const std::vector<InstDesc> &d
                 uint64_t *blob_bytes, uint64_t *desc_bytes, uint64_t *item_bytes);
 void prepare_scan_kernels();
 hipError_t launch_stream_read(const void *data, uint64_t n, uint32_t *out, uint32_t grid, hipStream_t s);
-hipError_t launch_segment_copy(const uint64_t *src, const CopySeg *segs, uint32_t nseg, hipStream_t s);
 
 // device translation unit
 uint32_t scan_lds_bytes(int cfg, uint32_t img_cap);

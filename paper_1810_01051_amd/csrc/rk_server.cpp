@@ -2,14 +2,18 @@
 //
 // Client threads append requests to a queue.  One scheduler thread owns a
 // private librk context and up to max_inflight stream slots.  For an idle
-// slot it takes waiting requests in arrival order, merges their patterns per
-// corpus (identical byte strings are searched once), builds a batch plan with
-// one instance per corpus and enqueues the count pass.  When a slot's count is
-// done the step is admitted once the output arena can hold its hits; then the
-// collect pass writes the hits and copies them to pinned host memory, and the
-// scheduler splits them per request.  Count and collect launches are captured
-// into HIP graphs per slot and replayed with each step's parameters
-// (hipGraphExecUpdate; re-instantiated when the launch sequence changes).
+// slot it takes waiting requests in arrival order and concatenates their
+// patterns per corpus, each request's patterns getting consecutive ids of the
+// merged set, so that its result is a contiguous slice of the merged output
+// (no copy per request; identical patterns of one step share their bytes in
+// the table image).  It builds a batch plan with one instance per corpus and
+// enqueues the count pass.  When a slot's count is done the step is admitted
+// once the output arena can hold its hits; a step that could never fit is
+// split and counted again.  Then the collect pass writes the sorted hits and
+// the per-pattern offsets come back to pinned host memory.  Count and collect
+// launches are captured into HIP graphs per slot and replayed with each
+// step's parameters (hipGraphExecUpdate; re-instantiated when the launch
+// sequence changes).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -34,6 +38,14 @@ namespace rk {
 
 static inline uint64_t aup(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
 
+// Device block holding the merged positions of one step; the requests of the
+// step own slices of it and the block goes back to the arena when the last of
+// them is released.
+struct StepBuf {
+  uint64_t off = 0, size = 0;
+  uint32_t refs = 0;
+};
+
 struct Request {
   uint64_t id = 0;
   uint32_t corpus = 0;
@@ -43,7 +55,8 @@ struct Request {
   rk_status status = RK_EBUSY;
   std::vector<uint64_t> res_offsets;  // host, k+1
   uint64_t out_off = 0, out_size = 0; // the request's positions in the arena (bytes)
-  std::vector<uint32_t> gpid;  // merged pattern id of each pattern within its step
+  StepBuf *buf = nullptr;             // block that holds them
+  uint32_t gp0 = 0;                   // merged id of the request's first pattern in its step
   double t_submit = 0, t_start = 0, t_done = 0;
   uint64_t step = 0;
 };
@@ -97,11 +110,11 @@ struct Arena {
   }
 };
 
-enum SlotState { kIdle, kCounting, kCounted, kCollecting, kDemuxing };
+enum SlotState { kIdle, kCounting, kCounted, kCollecting };
 
 struct Slot {
   hipStream_t stream = nullptr;
-  hipEvent_t ev_count = nullptr, ev_collect = nullptr, ev_demux = nullptr;
+  hipEvent_t ev_count = nullptr, ev_collect = nullptr;
   SlotState state = kIdle;
   rk_plan plan;
   void *dplan = nullptr;
@@ -112,19 +125,13 @@ struct Slot {
   uint64_t hstage_cap = 0;
   uint64_t *hres = nullptr;   // pinned: merged per-pattern offsets of the step
   uint64_t hres_cap = 0;      // bytes
-  CopySeg *hsegs = nullptr;   // pinned: demux segments
-  uint64_t hsegs_cap = 0;
-  void *dsegs = nullptr;      // device copy of the segments
-  uint64_t dsegs_cap = 0;
-  uint32_t max_mult = 1;      // largest number of request patterns sharing one merged pattern
   uint64_t *hctr = nullptr;   // pinned: total, overflow count
   hipGraphExec_t gcount = nullptr, gcollect = nullptr;
   std::vector<Request *> reqs;
   uint64_t step_id = 0, n_total = 0, total = 0, plan_bytes = 0;
   uint32_t ovf = 0;
-  uint64_t arena_off = 0, arena_size = 0;  // merged output + work of the step
-  uint64_t res_off = 0, res_size = 0;      // reservation for the per-request copies
-  uint64_t merged_pos_off = 0;             // merged positions inside the arena
+  uint64_t pos_off = 0, pos_size = 0;  // merged positions of the step (arena)
+  uint64_t aux_off = 0, aux_size = 0;  // per-pattern offsets and sort work (arena)
   double t_start = 0;
 };
 
@@ -155,7 +162,8 @@ struct rk_server {
   // statistics (under mu)
   std::vector<double> lat_ms;
   uint64_t submitted = 0, completed = 0, canceled = 0, failed = 0, steps = 0, bytes_scanned = 0;
-  uint64_t merged_patterns = 0, request_patterns = 0, admission_waits = 0;
+  uint64_t merged_patterns = 0, request_patterns = 0, admission_waits = 0, step_splits = 0;
+  uint32_t step_limit = 0;   // requests per step, lowered after a split and raised again
   double busy_s = 0, busy_since = 0;
   uint32_t inflight = 0;
   uint64_t outstanding = 0;  // submitted and not finished
@@ -252,7 +260,8 @@ static rk_status start_step(rk_server *S, Slot &sl, std::unique_lock<std::mutex>
   // take requests in arrival order
   std::vector<Request *> take;
   uint64_t pats = 0;
-  while (!S->pending.empty() && take.size() < S->cfg.max_step_requests) {
+  const uint32_t limit = std::min(S->cfg.max_step_requests, std::max<uint32_t>(S->step_limit, 1));
+  while (!S->pending.empty() && take.size() < limit) {
     Request *r = S->pending.front();
     if (!take.empty() && pats + r->k > S->cfg.max_step_patterns) break;
     S->pending.pop_front();
@@ -266,32 +275,21 @@ static rk_status start_step(rk_server *S, Slot &sl, std::unique_lock<std::mutex>
     r->step = step_id;
   }
   lk.unlock();
-  // merge patterns per corpus
+  // concatenate the requests' patterns per corpus: request i owns the merged
+  // ids [gp0, gp0 + k) of its corpus instance
   struct CB {
     std::vector<uint8_t> bytes;
     std::vector<uint64_t> offs{0};
-    std::unordered_map<std::string, uint32_t> index;
   };
   std::map<uint32_t, CB> by;
-  std::vector<std::vector<std::pair<uint32_t, uint32_t>>> local(take.size());
+  std::vector<uint32_t> local(take.size());
   for (size_t i = 0; i < take.size(); ++i) {
     Request *r = take[i];
     CB &cb = by[r->corpus];
-    local[i].resize(r->k);
-    for (uint32_t j = 0; j < r->k; ++j) {
-      std::string key((const char *)r->bytes.data() + r->offs[j], r->offs[j + 1] - r->offs[j]);
-      auto it = cb.index.find(key);
-      uint32_t idx;
-      if (it == cb.index.end()) {
-        idx = (uint32_t)(cb.offs.size() - 1);
-        cb.index.emplace(key, idx);
-        cb.bytes.insert(cb.bytes.end(), key.begin(), key.end());
-        cb.offs.push_back(cb.bytes.size());
-      } else {
-        idx = it->second;
-      }
-      local[i][j] = {r->corpus, idx};
-    }
+    local[i] = (uint32_t)(cb.offs.size() - 1);
+    const uint64_t b0 = cb.bytes.size();
+    cb.bytes.insert(cb.bytes.end(), r->bytes.begin(), r->bytes.end());
+    for (uint32_t j = 0; j < r->k; ++j) cb.offs.push_back(b0 + r->offs[j + 1]);
   }
   std::vector<rk_instance> inst;
   std::map<uint32_t, uint32_t> base;
@@ -309,16 +307,7 @@ static rk_status start_step(rk_server *S, Slot &sl, std::unique_lock<std::mutex>
     nbytes += I.n;
     inst.push_back(I);
   }
-  std::vector<uint32_t> mult(kt, 0);
-  for (size_t i = 0; i < take.size(); ++i) {
-    take[i]->gpid.resize(take[i]->k);
-    for (uint32_t j = 0; j < take[i]->k; ++j) {
-      take[i]->gpid[j] = base[local[i][j].first] + local[i][j].second;
-      ++mult[take[i]->gpid[j]];
-    }
-  }
-  sl.max_mult = 1;
-  for (uint32_t c : mult) sl.max_mult = std::max(sl.max_mult, c);
+  for (size_t i = 0; i < take.size(); ++i) take[i]->gp0 = base[take[i]->corpus] + local[i];
   // host plan
   sl.plan = rk_plan();
   std::vector<uint8_t> blob;
@@ -384,36 +373,66 @@ static rk_status start_step(rk_server *S, Slot &sl, std::unique_lock<std::mutex>
   return RK_OK;
 }
 
+static void release_slot(rk_server *S, Slot &sl) {
+  sl.state = kIdle;
+  if (--S->inflight == 0) S->busy_s += now_s() - S->busy_since;
+  S->cv_done.notify_all();
+}
+
+static void fail_step(rk_server *S, Slot &sl, rk_status st) {
+  for (Request *r : sl.reqs) finish_request(S, r, st);
+  sl.reqs.clear();
+  if (sl.pos_size) S->arena.release(sl.pos_off, sl.pos_size);
+  if (sl.aux_size) S->arena.release(sl.aux_off, sl.aux_size);
+  sl.pos_size = sl.aux_size = 0;
+  release_slot(S, sl);
+}
+
 // Admission and collect of a counted step (mu held).  Returns false if the
-// arena cannot hold it yet.  The step needs its merged output (per-pattern
-// offsets, positions, sort work) until the per-request copies are made, and
-// room for those copies (at most max_mult times the merged positions).
+// arena cannot hold it yet.  The step needs room for its merged positions
+// (kept until its requests are released) and for the per-pattern offsets and
+// the sort work (until the collect is done).  A step of several requests
+// larger than an equal share of the arena per slot is split: its requests go
+// back to the front of the queue and later steps take fewer requests.  A
+// single request larger than the whole arena fails with RK_ENOSPACE.
 static bool try_collect(rk_server *S, Slot &sl, std::unique_lock<std::mutex> &lk) {
   const uint32_t k = sl.plan.k_total;
-  const uint64_t off_b = aup((uint64_t)(k + 1) * 8, 256), pos_b = aup(std::max<uint64_t>(sl.total, 1) * 8, 256);
+  const uint64_t pos_b = aup(std::max<uint64_t>(sl.total, 1) * 8, 256);
+  const uint64_t off_b = aup((uint64_t)(k + 1) * 8, 256);
   const uint64_t work_b = aup(work_bytes_for(&sl.plan, sl.total), 256);
-  const uint64_t need = off_b + pos_b + work_b;
-  const uint64_t need_req = aup((uint64_t)sl.max_mult * sl.total * 8 + 256ull * sl.reqs.size(), 256);
+  const uint64_t need = pos_b + off_b + work_b;
+  const uint64_t share = S->arena.cap / S->slots.size();
   rk_status st = RK_OK;
-  if (need + need_req > S->arena.cap) {
-    st = set_err(S->ctx, RK_ENOSPACE, "step needs %llu arena bytes (arena %llu)",
-                 (unsigned long long)(need + need_req), (unsigned long long)S->arena.cap);
+  if (sl.reqs.size() > 1 && need > share) {
+    const uint64_t parts = std::max<uint64_t>(2, (need + share - 1) / std::max<uint64_t>(share, 1));
+    S->step_limit = (uint32_t)std::max<uint64_t>(1, sl.reqs.size() / parts);
+    for (auto it = sl.reqs.rbegin(); it != sl.reqs.rend(); ++it) S->pending.push_front(*it);
+    sl.reqs.clear();
+    ++S->step_splits;
+    release_slot(S, sl);
+    return true;
+  }
+  if (need > S->arena.cap) {
+    st = set_err(S->ctx, RK_ENOSPACE, "request needs %llu arena bytes (arena %llu)", (unsigned long long)need,
+                 (unsigned long long)S->arena.cap);
   } else {
-    uint64_t off, roff;
-    if (!S->arena.alloc(need, &off)) return false;
-    if (!S->arena.alloc(need_req, &roff)) {
-      S->arena.release(off, need);
+    uint64_t poff, aoff;
+    if (!S->arena.alloc(pos_b, &poff)) return false;
+    if (!S->arena.alloc(off_b + work_b, &aoff)) {
+      S->arena.release(poff, pos_b);
       return false;
     }
-    sl.arena_off = off;
-    sl.arena_size = need;
-    sl.res_off = roff;
-    sl.res_size = need_req;
-    sl.merged_pos_off = off + off_b;
+    sl.pos_off = poff;
+    sl.pos_size = pos_b;
+    sl.aux_off = aoff;
+    sl.aux_size = off_b + work_b;
+    // steps that use little of the arena let later steps take more requests
+    if (need * 4 <= share && S->step_limit < S->cfg.max_step_requests)
+      S->step_limit = (uint32_t)std::min<uint64_t>((uint64_t)S->step_limit * 2, S->cfg.max_step_requests);
     lk.unlock();
-    uint8_t *base = (uint8_t *)S->arena_dev + off;
-    uint64_t *doff = (uint64_t *)base, *dpos = (uint64_t *)(base + off_b);
-    void *work = work_b ? base + off_b + pos_b : nullptr;
+    uint8_t *aux = (uint8_t *)S->arena_dev + aoff;
+    uint64_t *doff = (uint64_t *)aux, *dpos = (uint64_t *)((uint8_t *)S->arena_dev + poff);
+    void *work = work_b ? aux + off_b : nullptr;
     hipError_t e = ensure_pinned(&sl.hres, &sl.hres_cap, (uint64_t)(k + 1) * 8);
     if (e != hipSuccess) st = hip_err(S->ctx, e, "offset staging");
     if (st == RK_OK)
@@ -433,95 +452,43 @@ static bool try_collect(rk_server *S, Slot &sl, std::unique_lock<std::mutex> &lk
       sl.state = kCollecting;
       return true;
     }
-    S->arena.release(sl.arena_off, sl.arena_size);
-    S->arena.release(sl.res_off, sl.res_size);
   }
-  for (Request *r : sl.reqs) finish_request(S, r, st);
-  sl.reqs.clear();
-  sl.state = kIdle;
-  if (--S->inflight == 0) S->busy_s += now_s() - S->busy_since;
-  S->cv_done.notify_all();
+  fail_step(S, sl, st);
   return true;
 }
 
-static void fail_step(rk_server *S, Slot &sl, rk_status st) {
-  for (Request *r : sl.reqs) finish_request(S, r, st);
-  sl.reqs.clear();
-  if (sl.arena_size) S->arena.release(sl.arena_off, sl.arena_size);
-  if (sl.res_size) S->arena.release(sl.res_off, sl.res_size);
-  sl.arena_size = sl.res_size = 0;
-  sl.state = kIdle;
-  if (--S->inflight == 0) S->busy_s += now_s() - S->busy_since;
-  S->cv_done.notify_all();
-}
-
-// Collected step: gives every request a contiguous slice of the arena and
-// enqueues the device copy of its patterns' hit lists (mu held).
-static void start_demux(rk_server *S, Slot &sl) {
-  const uint64_t *off = sl.hres;
-  constexpr uint64_t kSeg = 65536;
-  std::vector<CopySeg> segs;
-  // the reservation becomes the per-request slices (first fit lands inside it)
-  S->arena.release(sl.res_off, sl.res_size);
-  sl.res_size = 0;
-  for (Request *r : sl.reqs) {
-    r->res_offsets.assign(r->k + 1, 0);
-    uint64_t tot = 0;
-    for (uint32_t j = 0; j < r->k; ++j) {
-      const uint32_t g = r->gpid[j];
-      tot += off[g + 1] - off[g];
-      r->res_offsets[j + 1] = tot;
-    }
-    r->out_size = tot * 8;
-    r->out_off = 0;
-    if (tot && !S->arena.alloc(r->out_size, &r->out_off)) {
-      fail_step(S, sl, set_err(S->ctx, RK_ENOSPACE, "request slices do not fit the reservation"));
-      return;
-    }
-    uint64_t *dst = (uint64_t *)((uint8_t *)S->arena_dev + r->out_off);
-    for (uint32_t j = 0; j < r->k; ++j) {
-      const uint32_t g = r->gpid[j];
-      for (uint64_t a = off[g]; a < off[g + 1]; a += kSeg) {
-        CopySeg cs;
-        cs.src_off = a;
-        cs.dst = dst + r->res_offsets[j] + (a - off[g]);
-        cs.len = std::min<uint64_t>(kSeg, off[g + 1] - a);
-        segs.push_back(cs);
-      }
-    }
-  }
-  hipError_t e = ensure_pinned(&sl.hsegs, &sl.hsegs_cap, segs.size() * sizeof(CopySeg) + 64);
-  if (e == hipSuccess) e = ensure_dev(&sl.dsegs, &sl.dsegs_cap, segs.size() * sizeof(CopySeg) + 64);
-  if (e == hipSuccess && !segs.empty()) {
-    memcpy(sl.hsegs, segs.data(), segs.size() * sizeof(CopySeg));
-    e = hipMemcpyAsync(sl.dsegs, sl.hsegs, segs.size() * sizeof(CopySeg), hipMemcpyHostToDevice, sl.stream);
-    if (e == hipSuccess)
-      e = launch_segment_copy((const uint64_t *)((uint8_t *)S->arena_dev + sl.merged_pos_off),
-                              (const CopySeg *)sl.dsegs, (uint32_t)segs.size(), sl.stream);
-  }
-  if (e == hipSuccess) e = hipEventRecord(sl.ev_demux, sl.stream);
-  if (e != hipSuccess) {
-    for (Request *r : sl.reqs)
-      if (r->out_size) S->arena.release(r->out_off, r->out_size), r->out_size = 0;
-    fail_step(S, sl, hip_err(S->ctx, e, "demux"));
+// Collected step: every request gets its slice of the merged positions and
+// its own offsets; the per-pattern offsets and the sort work go back to the
+// arena (mu held).
+static void finish_collect(rk_server *S, Slot &sl) {
+  StepBuf *buf = new (std::nothrow) StepBuf();
+  if (!buf) {
+    fail_step(S, sl, set_err(S->ctx, RK_ENOMEM, "step buffer"));
     return;
   }
-  sl.state = kDemuxing;
-}
-
-// Demuxed step: the merged output is freed, the requests are done (mu held).
-static void finish_step(rk_server *S, Slot &sl) {
+  buf->off = sl.pos_off;
+  buf->size = sl.pos_size;
+  buf->refs = (uint32_t)sl.reqs.size();
+  const uint64_t *off = sl.hres;
   for (Request *r : sl.reqs) {
+    const uint64_t b = off[r->gp0];
+    r->res_offsets.resize(r->k + 1);
+    for (uint32_t j = 0; j <= r->k; ++j) r->res_offsets[j] = off[r->gp0 + j] - b;
+    r->out_off = sl.pos_off + b * 8;
+    r->out_size = r->res_offsets[r->k] * 8;
+    r->buf = buf;
     r->bytes.clear();
     r->bytes.shrink_to_fit();
     finish_request(S, r, RK_OK);
   }
+  if (sl.reqs.empty()) {
+    S->arena.release(buf->off, buf->size);
+    delete buf;
+  }
   sl.reqs.clear();
-  S->arena.release(sl.arena_off, sl.arena_size);
-  sl.arena_size = 0;
-  sl.state = kIdle;
-  if (--S->inflight == 0) S->busy_s += now_s() - S->busy_since;
-  S->cv_done.notify_all();
+  S->arena.release(sl.aux_off, sl.aux_size);
+  sl.pos_size = sl.aux_size = 0;  // the positions now belong to the requests
+  release_slot(S, sl);
 }
 
 static void scheduler(rk_server *S) {
@@ -548,21 +515,10 @@ static void scheduler(rk_server *S) {
       if (sl.state == kCollecting) {
         const hipError_t q = hipEventQuery(sl.ev_collect);
         if (q == hipSuccess) {
-          start_demux(S, sl);
+          finish_collect(S, sl);
           progress = true;
         } else if (q != hipErrorNotReady) {
           fail_step(S, sl, hip_err(S->ctx, q, "collect pass"));
-        }
-      }
-      if (sl.state == kDemuxing) {
-        const hipError_t q = hipEventQuery(sl.ev_demux);
-        if (q == hipSuccess) {
-          finish_step(S, sl);
-          progress = true;
-        } else if (q != hipErrorNotReady) {
-          for (Request *r : sl.reqs)
-            if (r->out_size) S->arena.release(r->out_off, r->out_size), r->out_size = 0;
-          fail_step(S, sl, hip_err(S->ctx, q, "demux copy"));
         }
       }
     }
@@ -635,12 +591,12 @@ rk_status rk_server_create(rk_ctx *ctx, const rk_server_cfg *cfg_in, rk_server *
     return set_err(ctx, RK_ENOMEM, "server arena (%llu bytes)", (unsigned long long)cfg.arena_bytes);
   }
   S->arena.init(cfg.arena_bytes);
+  S->step_limit = cfg.max_step_requests;
   S->slots.resize(cfg.max_inflight);
   for (Slot &sl : S->slots) {
     e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.ev_count, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.ev_collect, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.ev_demux, hipEventDisableTiming);
     if (e == hipSuccess) e = hipHostMalloc((void **)&sl.hctr, 64, hipHostMallocDefault);
     if (e != hipSuccess) break;
   }
@@ -761,8 +717,12 @@ rk_status rk_server_release(rk_server *S, uint64_t id) {
   auto it = S->reqs.find(id);
   if (it == S->reqs.end()) return RK_EINVAL;
   if (it->second->status == RK_EBUSY) return RK_EBUSY;
-  if (it->second->out_size) S->arena.release(it->second->out_off, it->second->out_size);
-  delete it->second;
+  Request *r = it->second;
+  if (r->buf && --r->buf->refs == 0) {
+    S->arena.release(r->buf->off, r->buf->size);
+    delete r->buf;
+  }
+  delete r;
   S->reqs.erase(it);
   return RK_OK;
 }
@@ -814,6 +774,7 @@ rk_status rk_server_get_stats(rk_server *S, rk_server_stats *o) {
   o->queue_depth = (uint32_t)S->pending.size();
   o->inflight = S->inflight;
   o->admission_waits = S->admission_waits;
+  o->step_splits = S->step_splits;
   if (!S->lat_ms.empty()) {
     std::vector<double> v = S->lat_ms;
     std::sort(v.begin(), v.end());
@@ -833,7 +794,7 @@ rk_status rk_server_reset_stats(rk_server *S) {
   std::lock_guard<std::mutex> g(S->mu);
   S->lat_ms.clear();
   S->completed = S->canceled = S->failed = S->steps = S->bytes_scanned = 0;
-  S->merged_patterns = S->request_patterns = S->admission_waits = 0;
+  S->merged_patterns = S->request_patterns = S->admission_waits = S->step_splits = 0;
   S->submitted = S->outstanding;
   S->busy_s = 0;
   if (S->inflight) S->busy_since = now_s();
@@ -858,9 +819,6 @@ void rk_server_destroy(rk_server *S) {
     drop_graphs(sl);
     if (sl.ev_count) hipEventDestroy(sl.ev_count);
     if (sl.ev_collect) hipEventDestroy(sl.ev_collect);
-    if (sl.ev_demux) hipEventDestroy(sl.ev_demux);
-    if (sl.hsegs) hipHostFree(sl.hsegs);
-    if (sl.dsegs) hipFree(sl.dsegs);
     if (sl.stream) hipStreamDestroy(sl.stream);
     if (sl.dplan) hipFree(sl.dplan);
     if (sl.scratch) hipFree(sl.scratch);
@@ -869,7 +827,11 @@ void rk_server_destroy(rk_server *S) {
     if (sl.hctr) hipHostFree(sl.hctr);
   }
   if (S->arena_dev) hipFree(S->arena_dev);
-  for (auto &kv : S->reqs) delete kv.second;
+  for (auto &kv : S->reqs) {
+    Request *r = kv.second;
+    if (r->buf && --r->buf->refs == 0) delete r->buf;
+    delete r;
+  }
   if (S->ctx) rk_ctx_destroy(S->ctx);
   delete S;
 }

@@ -119,6 +119,47 @@ def test_random_small(ctx, rk, mode):
 
 
 @pytest.mark.parametrize("mode", MODES)
+def test_many_patterns_per_length(ctx, rk, mode):
+    """Hash-table buckets: dozens of distinct patterns per length, lengths
+    1..3 (masked screen hashes) as well as longer ones, sampled and random,
+    over small and large alphabets."""
+    g = rkgen.rng(52, 1 if mode == "screen" else 2)
+    for trial, table in enumerate([rkgen.ACGT, rkgen.LOWER, rkgen.BYTE256]):
+        n = 200000
+        text = rkgen.iid_text(g, n, table)
+        pats = []
+        for m in (1, 2, 3, 4, 5, 7, 8, 12, 16, 17, 31, 64):
+            for j in range(40):
+                if j % 2 == 0:
+                    o = int(g.integers(0, n - m + 1))
+                    pats.append(text[o:o + m].tobytes())
+                else:
+                    pats.append(rkgen.iid_text(g, m, table).tobytes())
+        got = run(ctx, rk, text, pats, mode)
+        assert_same(got, oracle.search(text, pats, threads=4), "trial %d" % trial)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_large_pattern_set(ctx, rk, mode):
+    """Thousands of patterns of mixed lengths in one plan (several table
+    buckets and cuckoo tables, patterns read from device memory)."""
+    g = rkgen.rng(53, 1 if mode == "screen" else 2)
+    n = 1 << 20
+    text = rkgen.iid_text(g, n, rkgen.LOWER)
+    pats = []
+    for j in range(6000):
+        m = int(g.integers(4, 65))
+        if j % 3 == 0:
+            o = int(g.integers(0, n - m + 1))
+            pats.append(text[o:o + m].tobytes())
+        else:
+            pats.append(rkgen.iid_text(g, m, rkgen.LOWER).tobytes())
+    pats += pats[:50]  # duplicates: each copy gets the full list
+    got = run(ctx, rk, text, pats, mode)
+    assert_same(got, oracle.search(text, pats, threads=8), mode)
+
+
+@pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("cfg", [0, 1, 2, 3])
 def test_tile_seams_every_geometry(ctx, rk, mode, cfg):
     """Occurrences planted across tile and thread seams, first and last window."""
