@@ -341,7 +341,11 @@ def bench_config5(args):
 
         def releaser():
             i = 0
+            t_last = time.perf_counter()
             while i < len(reqs):
+                if time.perf_counter() - t_last > 5:
+                    t_last = time.perf_counter()
+                    log("config5 rate %g: %d/%d requests done" % (rate, i, len(reqs)))
                 if rids[i] is None:
                     if stop.is_set():
                         return

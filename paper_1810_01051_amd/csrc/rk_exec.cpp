@@ -171,7 +171,10 @@ rk_status make_layout(rk_ctx *ctx, const rk_plan *plan, uint64_t n, Layout &L) {
     L.T1 = (n + L.W - 1) / L.W;
     L.T = L.T1 * plan->vinsts.size();
   }
-  L.S = ctx->slab_cap ? ctx->slab_cap : L.W / 64;
+  // staging records per tile: one per 64 text bytes for a single pattern
+  // (hits are rare), one per 16 for pattern sets (sampled patterns hit often);
+  // a tile with more hits is rescanned by the collect pass
+  L.S = ctx->slab_cap ? ctx->slab_cap : (plan->k_total > 1 ? L.W / 16 : L.W / 64);
   uint64_t o = 0;
   auto take = [&o](uint64_t bytes) {
     const uint64_t r = o;

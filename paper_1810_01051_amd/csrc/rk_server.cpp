@@ -581,6 +581,9 @@ rk_status rk_server_create(rk_ctx *ctx, const rk_server_cfg *cfg_in, rk_server *
   }
   // fixed persistent grid: no occupancy query while a stream is being captured
   S->ctx->grid = (uint32_t)S->ctx->num_cu * 4;
+  // staging records per tile: a step may scan every corpus, so the slabs are
+  // kept to a quarter of the text bytes (denser tiles are rescanned)
+  S->ctx->slab_cap = 544;
   for (int md = 0; md < 3; ++md)
     for (int m = 0; m <= RK_MAX_M; ++m) S->ctx->tune[md][m] = ctx->tune[md][m];
   S->ctx->tile_cfg = ctx->tile_cfg;
