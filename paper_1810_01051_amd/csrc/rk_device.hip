@@ -527,6 +527,16 @@ __device__ __forceinline__ void dma_tile(uint8_t *slot, const uint8_t *text, uin
   constexpr uint32_t W = WG * C, J = W / 1024, NW = WG / 64;
   static_assert(W % 1024 == 0, "a tile is a whole number of 1 KiB wave loads");
   const uint32_t lane = threadIdx.x & 63, wave = uni(threadIdx.x >> 6);
+  if (tstart >= (int64_t)kFront && (uint64_t)tstart + W <= n) {
+    // interior tile: every chunk is text
+    const uint8_t *base = text + tstart + 16u * lane;
+    for (uint32_t j = wave; j < J; j += NW)
+      __builtin_amdgcn_global_load_lds((const void *)(base + 1024u * j), (lds_void_t *)(slot + kFront + 1024u * j), 16,
+                                       0, 0);
+    if (wave == NW - 1 && lane < 4)
+      __builtin_amdgcn_global_load_lds((const void *)(base - kFront), (lds_void_t *)slot, 16, 0, 0);
+    return;
+  }
   for (uint32_t j = wave; j < J; j += NW) {
     const uint64_t g = (uint64_t)tstart + 1024u * j + 16u * lane;
     const uint8_t *src = g < n ? text + g : text;
@@ -536,6 +546,99 @@ __device__ __forceinline__ void dma_tile(uint8_t *slot, const uint8_t *text, uin
     const int64_t g = tstart - (int64_t)kFront + 16 * (int64_t)lane;
     const uint8_t *src = g >= 0 ? text + g : text;
     __builtin_amdgcn_global_load_lds((const void *)src, (lds_void_t *)slot, 16, 0, 0);
+  }
+}
+
+// Candidate phase of one bucket on one tile.  bits holds the thread's
+// candidate mask (window i of the thread at bit word_windows-1-(i%32) of word
+// i/32).  Windows that start before the text or end after it are dropped, the
+// candidates are compacted block-wide into the LDS list in window order, and
+// each is checked by one thread: key recomputed, key table, byte comparison
+// with every pattern chained under the key.  Hits go to the tile's slab (up to
+// cap records) in window order; tile_hits counts them all.  ncand returns the
+// number of candidates (block-uniform).
+template <int WG, int C>
+__device__ __forceinline__ void candidate_phase(Bits<C> &bits, const BucketDesc &D, const uint8_t *tile, int64_t tstart,
+                                                uint64_t n, int64_t e0, const uint8_t *gimg, uint32_t *cand,
+                                                uint32_t *misc, uint64_t *slab, uint32_t cap, uint32_t &tile_hits,
+                                                uint32_t &ncand) {
+  constexpr uint32_t W = WG * C;
+  constexpr int NB = (C + 31) / 32;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t m = D.m;
+  // only windows with m-1 <= e <= n-1 exist
+  const bool edge = tstart < (int64_t)m - 1 || (uint64_t)(tstart + W) > n;
+  if (edge) {
+    // my windows i are valid for ilo <= i < ihi
+    const int64_t lo64 = (int64_t)m - 1 - e0, hi64 = (int64_t)n - e0;
+    const int ilo = (int)(lo64 < 0 ? 0 : (lo64 > C ? C : lo64));
+    const int ihi = (int)(hi64 < 0 ? 0 : (hi64 > C ? C : hi64));
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int nw = word_windows<C>(j);
+      int a = ilo - 32 * j, b2 = ihi - 32 * j;
+      a = a < 0 ? 0 : (a > nw ? nw : a);
+      b2 = b2 < 0 ? 0 : (b2 > nw ? nw : b2);
+      // local window k sits at bit nw-1-k: keep bits [nw-b2, nw-a)
+      const uint32_t below_hi = (nw - a) >= 32 ? 0xFFFFFFFFu : ((1u << (nw - a)) - 1u);
+      const uint32_t below_lo = (nw - b2) >= 32 ? 0xFFFFFFFFu : ((1u << (nw - b2)) - 1u);
+      bits.b[j] &= (b2 > a) ? (below_hi & ~below_lo) : 0u;
+    }
+  }
+  uint32_t cnt = 0;
+#pragma unroll
+  for (int j = 0; j < NB; ++j) cnt += __builtin_popcount(bits.b[j]);
+  const uint32_t cbase = block_excl_scan<WG>(cnt, misc, ncand);
+
+  for (uint32_t r0 = 0; r0 < ncand; r0 += kCandCap) {
+    wg_barrier();  // cand list free
+    if (cnt) {
+      uint32_t idx = cbase;
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        uint32_t bb = bits.b[j];
+        while (bb) {
+          const uint32_t hb = 31u - __builtin_clz(bb);  // highest bit = earliest window
+          const uint32_t i = 32u * j + (uint32_t)word_windows<C>(j) - 1u - hb;
+          bb &= ~(1u << hb);
+          if (idx >= r0 && idx < r0 + kCandCap) cand[idx - r0] = tid * C + i;
+          ++idx;
+        }
+      }
+    }
+    wg_barrier();
+    const uint32_t nc = min(kCandCap, ncand - r0);
+    for (uint32_t i0 = 0; i0 < nc; i0 += WG) {
+      const uint32_t ci = i0 + tid;
+      uint32_t run = kNoLink, nh = 0, hmask = 0;
+      const uint8_t *end = nullptr;
+      int64_t e = 0;
+      const bool screen = D.kind == kListScreen || D.kind == kTableScreen;
+      if (ci < nc) {
+        const uint32_t e_rel = cand[ci];
+        end = tile + kFront + e_rel;
+        e = tstart + (int64_t)e_rel;
+        const uint64_t key = screen ? (uint64_t)screen_key(end, D.shift & 0xFFu, D.mask)
+                                    : horner_exact(end - (m - 1), m);
+        run = key_lookup(gimg, D, key);
+        nh = verify_run(gimg, D, run, end, e, hmask);
+      }
+      uint32_t nht;
+      const uint32_t hb = block_excl_scan<WG>(nh, misc, nht);
+      if (nh) {
+        uint32_t o = tile_hits + hb;
+        const Entry *ent = (const Entry *)(gimg + D.ent_off);
+        const uint32_t first = run & 0xFFFFu, cnt = run >> 16;
+        for (uint32_t i = 0; i < cnt; ++i) {
+          const Entry en = ent[first + i];
+          if (!entry_hit(gimg, D, en, i, hmask, end, e)) continue;
+          const uint64_t x = (uint64_t)(e - (int64_t)(en.off_m >> 24) + 1);
+          if (o < cap) slab[o] = ((uint64_t)en.pid << kPosBits) | x;
+          ++o;
+        }
+      }
+      tile_hits += nht;
+    }
   }
 }
 
@@ -701,82 +804,9 @@ __global__ __launch_bounds__(WG) void scan_kernel(ScanParams p) {
       for (int j = 0; j < NB; ++j) bits.b[j] = 0;
       uint64_t dummy = 0;
       run_pass<C, false, FAM>(D, tw, os, r, fp, dummy, bits);
-      // only windows with m-1 <= e <= n-1 exist
-      const bool edge = tstart < (int64_t)m - 1 || (uint64_t)(tstart + W) > n;
-      if (edge) {
-        // my windows i are valid for ilo <= i < ihi
-        const int64_t lo64 = (int64_t)m - 1 - e0, hi64 = (int64_t)n - e0;
-        const int ilo = (int)(lo64 < 0 ? 0 : (lo64 > C ? C : lo64));
-        const int ihi = (int)(hi64 < 0 ? 0 : (hi64 > C ? C : hi64));
-#pragma unroll
-        for (int j = 0; j < NB; ++j) {
-          const int nw = word_windows<C>(j);
-          int a = ilo - 32 * j, b2 = ihi - 32 * j;
-          a = a < 0 ? 0 : (a > nw ? nw : a);
-          b2 = b2 < 0 ? 0 : (b2 > nw ? nw : b2);
-          // local window k sits at bit nw-1-k: keep bits [nw-b2, nw-a)
-          const uint32_t below_hi = (nw - a) >= 32 ? 0xFFFFFFFFu : ((1u << (nw - a)) - 1u);
-          const uint32_t below_lo = (nw - b2) >= 32 ? 0xFFFFFFFFu : ((1u << (nw - b2)) - 1u);
-          bits.b[j] &= (b2 > a) ? (below_hi & ~below_lo) : 0u;
-        }
-      }
-      uint32_t cnt = 0;
-#pragma unroll
-      for (int j = 0; j < NB; ++j) cnt += __builtin_popcount(bits.b[j]);
       uint32_t ncand;
-      const uint32_t cbase = block_excl_scan<WG>(cnt, misc, ncand);
+      candidate_phase<WG, C>(bits, D, tile, tstart, n, e0, gimg, cand, misc, slab, cap, tile_hits, ncand);
       if (b < 32) dense_mask = ncand ? (dense_mask | (1u << b)) : (dense_mask & ~(1u << b));
-
-      for (uint32_t r0 = 0; r0 < ncand; r0 += kCandCap) {
-        wg_barrier();  // cand list free
-        if (cnt) {
-          uint32_t idx = cbase;
-#pragma unroll
-          for (int j = 0; j < NB; ++j) {
-            uint32_t bb = bits.b[j];
-            while (bb) {
-              const uint32_t hb = 31u - __builtin_clz(bb);  // highest bit = earliest window
-              const uint32_t i = 32u * j + (uint32_t)word_windows<C>(j) - 1u - hb;
-              bb &= ~(1u << hb);
-              if (idx >= r0 && idx < r0 + kCandCap) cand[idx - r0] = tid * C + i;
-              ++idx;
-            }
-          }
-        }
-        wg_barrier();
-        const uint32_t nc = min(kCandCap, ncand - r0);
-        for (uint32_t i0 = 0; i0 < nc; i0 += WG) {
-          const uint32_t ci = i0 + tid;
-          uint32_t run = kNoLink, nh = 0, hmask = 0;
-          const uint8_t *end = nullptr;
-          int64_t e = 0;
-          const bool screen = D.kind == kListScreen || D.kind == kTableScreen;
-          if (ci < nc) {
-            const uint32_t e_rel = cand[ci];
-            end = tile + kFront + e_rel;
-            e = tstart + (int64_t)e_rel;
-            const uint64_t key = screen ? (uint64_t)screen_key(end, D.shift & 0xFFu, D.mask)
-                                        : horner_exact(end - (m - 1), m);
-            run = key_lookup(gimg, D, key);
-            nh = verify_run(gimg, D, run, end, e, hmask);
-          }
-          uint32_t nht;
-          const uint32_t hb = block_excl_scan<WG>(nh, misc, nht);
-          if (nh) {
-            uint32_t o = tile_hits + hb;
-            const Entry *ent = (const Entry *)(gimg + D.ent_off);
-            const uint32_t first = run & 0xFFFFu, cnt = run >> 16;
-            for (uint32_t i = 0; i < cnt; ++i) {
-              const Entry en = ent[first + i];
-              if (!entry_hit(gimg, D, en, i, hmask, end, e)) continue;
-              const uint64_t x = (uint64_t)(e - (int64_t)(en.off_m >> 24) + 1);
-              if (o < cap) slab[o] = ((uint64_t)en.pid << kPosBits) | x;
-              ++o;
-            }
-          }
-          tile_hits += nht;
-        }
-      }
     }
 
     if (tid == 0 && !p.direct) {
@@ -789,6 +819,80 @@ __global__ __launch_bounds__(WG) void scan_kernel(ScanParams p) {
     }
     item = next;
     cur = nx;
+    slot ^= 1u;
+  }
+}
+
+// ------------------------------------------------- single-bucket scan kernel
+// The same scan for the most common plan shape: one text and one bucket whose
+// set fits in registers (up to 4 targets: one pattern, or a few patterns of
+// similar length).  The bucket descriptor and the text come as kernel
+// arguments, tiles are strided statically over the persistent grid, and there
+// is no image staging, work list or instance lookup, so a tile costs little
+// beyond its hash pass.  Count mode only (hits into per-tile slabs); a tile
+// whose slab overflows is rescanned by the general kernel.
+//
+// LDS: [slot 0][slot 1][cand: kCandCap u32][misc: 64 u32]
+template <int WG, int C, int FAM>
+__global__ __launch_bounds__(WG) void scan_list_kernel(ListParams p) {
+  constexpr uint32_t W = WG * C;
+  constexpr uint32_t TILE_LDS = (kFront + W + 16 + 15) & ~15u;
+  constexpr int NB = (C + 31) / 32;
+  extern __shared__ __align__(16) uint8_t lds[];
+  uint32_t *cand = (uint32_t *)(lds + 2 * TILE_LDS);
+  uint32_t *misc = cand + kCandCap;
+  const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const BucketDesc D = p.D;
+  const uint32_t m = D.m;
+  const uint32_t r = p.rot;
+  uint32_t slot = 0, flag_parity = 0;
+  bool dense = false;
+  uint64_t t = blockIdx.x;
+  if (t < p.ntiles) dma_tile<WG, C>(lds, p.text, p.n, (int64_t)(t * W));
+  while (t < p.ntiles) {
+    const uint64_t nt = t + gridDim.x;
+    wg_barrier_loads();  // tile t has landed; every wave is done with the other slot
+    const uint8_t *tile = lds + slot * TILE_LDS;
+    const int64_t tstart = (int64_t)(t * W);
+    if (nt < p.ntiles) dma_tile<WG, C>(lds + (slot ^ 1u) * TILE_LDS, p.text, p.n, (int64_t)(nt * W));
+    const uint32_t *tw = (const uint32_t *)(tile + kFront + tid * C - 64);
+    const OutStream os = out_stream(tile + kFront + tid * C, m);
+    const int64_t e0 = tstart + (int64_t)(tid * C);
+    uint32_t tile_hits = 0;
+    bool run2 = dense;
+    if (!dense) {
+      uint64_t any = 0;
+      Bits<C> nob;
+      run_pass<C, true, FAM>(D, tw, os, r, nullptr, any, nob);
+      uint32_t *flags = misc + 16 + 16 * flag_parity;
+      flag_parity ^= 1u;
+      if (lane == 0) flags[wave] = any != 0;
+      wg_barrier();
+      uint32_t blk_any = 0;
+#pragma unroll
+      for (int i = 0; i < WG / 64; ++i) blk_any |= flags[i];
+      run2 = blk_any != 0;
+    }
+    if (run2) {
+      Bits<C> bits;
+#pragma unroll
+      for (int j = 0; j < NB; ++j) bits.b[j] = 0;
+      uint64_t dummy = 0;
+      run_pass<C, false, FAM>(D, tw, os, r, nullptr, dummy, bits);
+      uint32_t ncand;
+      candidate_phase<WG, C>(bits, D, tile, tstart, p.n, e0, p.gimg, cand, misc, p.out + t * (uint64_t)p.slab_cap,
+                             p.slab_cap, tile_hits, ncand);
+      dense = ncand != 0;
+    }
+    if (tid == 0) {
+      p.tile_counts[t] = tile_hits;
+      if (tile_hits) atomicAdd(p.total, (unsigned long long)tile_hits);
+      if (tile_hits > p.slab_cap) {
+        const uint32_t o = atomicAdd(p.ovf_count, 1u);
+        p.ovf_list[o] = t;
+      }
+    }
+    t = nt;
     slot ^= 1u;
   }
 }
@@ -999,6 +1103,11 @@ __global__ void window_hashes_kernel(const uint8_t *text, uint64_t n, uint32_t m
 }
 
 // ------------------------------------------------------------------ launchers
+template <int WG, int C>
+static constexpr uint32_t list_lds_bytes_t() {
+  return 2 * ((kFront + WG * C + 16 + 15) & ~15u) + kCandCap * 4 + 64 * 4;
+}
+
 template <int WG, int C, int FAM>
 static hipError_t launch_scan_t(const ScanParams &p, uint32_t grid, uint32_t lds_bytes, hipStream_t s) {
   // the dynamic LDS limit was raised by prepare_scan_kernels() at context creation
@@ -1139,6 +1248,41 @@ hipError_t launch_window_hashes(const uint8_t *text, uint64_t n, uint32_t m, con
 
 // Raises the dynamic LDS limit of every scan kernel once, outside any stream
 // capture (a graph capture must not run first-time setup calls).
+template <int WG, int C, int FAM>
+static hipError_t launch_list_t(const ListParams &p, uint32_t grid, hipStream_t s) {
+  constexpr uint32_t lds = list_lds_bytes_t<WG, C>();
+  hipLaunchKernelGGL((scan_list_kernel<WG, C, FAM>), dim3(grid), dim3(WG), lds, s, p);
+  return hipGetLastError();
+}
+
+template <int WG, int C, int FAM>
+static hipError_t occ_list_t(int *blocks) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, (const void *)scan_list_kernel<WG, C, FAM>, WG,
+                                                      list_lds_bytes_t<WG, C>());
+}
+
+template <int FAM>
+static hipError_t list_fam(int cfg, const ListParams *p, uint32_t grid, hipStream_t s, int *blocks) {
+  switch (cfg) {
+    case 0: return p ? launch_list_t<256, 68, FAM>(*p, grid, s) : occ_list_t<256, 68, FAM>(blocks);
+    case 1: return p ? launch_list_t<256, 132, FAM>(*p, grid, s) : occ_list_t<256, 132, FAM>(blocks);
+    case 2: return p ? launch_list_t<512, 68, FAM>(*p, grid, s) : occ_list_t<512, 68, FAM>(blocks);
+    case 3: return p ? launch_list_t<256, 36, FAM>(*p, grid, s) : occ_list_t<256, 36, FAM>(blocks);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// Launches (p != nullptr) or sizes (occupancy into *blocks) the single-bucket
+// scan of geometry cfg and family fam.
+hipError_t list_scan(int cfg, int fam, const ListParams *p, uint32_t grid, hipStream_t s, int *blocks) {
+  switch (fam) {
+    case kFamScreen1: return list_fam<kFamScreen1>(cfg, p, grid, s, blocks);
+    case kFamScreen: return list_fam<kFamScreen>(cfg, p, grid, s, blocks);
+    case kFamExact: return list_fam<kFamExact>(cfg, p, grid, s, blocks);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 template <int FAM>
 static void prepare_fam() {
   (void)hipFuncSetAttribute((const void *)scan_kernel<256, 68, FAM>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1148,6 +1292,14 @@ static void prepare_fam() {
   (void)hipFuncSetAttribute((const void *)scan_kernel<512, 68, FAM>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             160 * 1024);
   (void)hipFuncSetAttribute((const void *)scan_kernel<256, 36, FAM>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            160 * 1024);
+  (void)hipFuncSetAttribute((const void *)scan_list_kernel<256, 68, FAM>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            160 * 1024);
+  (void)hipFuncSetAttribute((const void *)scan_list_kernel<256, 132, FAM>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            160 * 1024);
+  (void)hipFuncSetAttribute((const void *)scan_list_kernel<512, 68, FAM>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            160 * 1024);
+  (void)hipFuncSetAttribute((const void *)scan_list_kernel<256, 36, FAM>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             160 * 1024);
 }
 

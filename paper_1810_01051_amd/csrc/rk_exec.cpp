@@ -81,6 +81,10 @@ rk_status plan_build_host(rk_ctx *ctx, const rk_instance *inst, uint32_t count, 
   for (const VInst &v : P->vinsts)
     if (mode != RK_MODE_EXACT && !v.only_one_list) P->fam = kFamScreen;
   for (const VInst &v : P->vinsts) P->img_cap = std::max(P->img_cap, v.lds_bytes);
+  if (!batch && P->vinsts.size() == 1 && P->vinsts[0].nbuckets == 1) {
+    memcpy(&P->list_desc, blob.data() + P->vinsts[0].img_off + sizeof(ImageHeader), sizeof(BucketDesc));
+    P->list1 = P->list_desc.kind == kListScreen || P->list_desc.kind == kListExact;
+  }
   P->img_cap = (uint32_t)align_up(P->img_cap, 16);
   if (batch) {
     const uint32_t W = kTileCfgs[P->cfg].wg * kTileCfgs[P->cfg].c;
@@ -330,14 +334,45 @@ rk_status count_enqueue(rk_ctx *ctx, const rk_plan *plan, const uint8_t *text, u
     p.grab = 1;
   }
   const uint32_t lds = scan_lds_bytes(plan->cfg, plan->img_cap);
-  const uint32_t grid = scan_grid(ctx, plan->cfg, plan->fam, lds, p.nitems);
   int slot;
+  if (plan->list1 && !use_queue) {
+    // one text, one bucket with register targets: the single-bucket kernel
+    ListParams lp;
+    memset(&lp, 0, sizeof lp);
+    lp.text = text;
+    lp.n = n;
+    lp.ntiles = L.T;
+    lp.gimg = plan->blob_dev + plan->vinsts[0].img_off;
+    lp.D = plan->list_desc;
+    lp.rot = (8u * plan->list_desc.m) % 61u;
+    lp.slab_cap = L.S;
+    lp.tile_counts = p.tile_counts;
+    lp.out = p.out;
+    lp.total = p.total;
+    lp.ovf_count = p.ovf_count;
+    lp.ovf_list = p.ovf_list;
+    uint32_t grid = ctx->grid;
+    if (!grid) {
+      int blocks = 0;
+      if (list_scan(plan->cfg, plan->fam, nullptr, 0, nullptr, &blocks) != hipSuccess || blocks < 1) blocks = 1;
+      grid = (uint32_t)ctx->num_cu * (uint32_t)blocks;
+    }
+    grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(grid, L.T));
+    e = prof_begin(ctx, s, 0, &slot);
+    if (e != hipSuccess) return hip_err(ctx, e, "profiling event");
+    e = list_scan(plan->cfg, plan->fam, &lp, grid, s, nullptr);
+    if (e != hipSuccess) return hip_err(ctx, e, "scan launch");
+    e = prof_end(ctx, s, slot);
+    if (e != hipSuccess) return hip_err(ctx, e, "profiling event");
+  } else {
+  const uint32_t grid = scan_grid(ctx, plan->cfg, plan->fam, lds, p.nitems);
   e = prof_begin(ctx, s, 0, &slot);
   if (e != hipSuccess) return hip_err(ctx, e, "profiling event");
   e = launch_scan(plan->cfg, plan->fam, p, grid, lds, s);
   if (e != hipSuccess) return hip_err(ctx, e, "scan launch");
   e = prof_end(ctx, s, slot);
   if (e != hipSuccess) return hip_err(ctx, e, "profiling event");
+  }
   CountMemo &mm = ctx->memo[ctx->memo_next++ % 16];
   mm.scratch = scratch;
   mm.plan = plan;

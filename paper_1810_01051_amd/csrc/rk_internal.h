@@ -112,6 +112,23 @@ struct ScanParams {
   uint64_t dump_cap;
 };
 
+// Kernel parameters of the single-bucket scan (one text, one bucket whose set
+// sits in registers; count mode).
+struct ListParams {
+  const uint8_t *text;        // 16-byte aligned
+  uint64_t n;
+  uint64_t ntiles;
+  const uint8_t *gimg;        // the instance image in device memory (verification tables)
+  BucketDesc D;               // the bucket (offsets relative to gimg)
+  uint32_t rot;               // 8 m mod 61
+  uint32_t slab_cap;
+  uint32_t *tile_counts;
+  uint64_t *out;              // slabs [tile][slab_cap]
+  unsigned long long *total;
+  uint32_t *ovf_count;
+  uint64_t *ovf_list;
+};
+
 // Host-side geometry table (workgroup size, windows per thread).
 struct TileCfg {
   uint32_t wg;

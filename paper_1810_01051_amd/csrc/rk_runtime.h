@@ -73,6 +73,8 @@ struct rk_plan {
   int fam = rk::kFamScreen1;
   uint32_t k_total = 0;
   uint32_t img_cap = 0;       // LDS bytes reserved for images (max image size)
+  bool list1 = false;         // one text, one bucket with register targets: single-bucket kernel
+  rk::BucketDesc list_desc;   // that bucket
   uint64_t text_bytes = 0;
   std::vector<rk::RealInst> insts;
   std::vector<rk::VInst> vinsts;
@@ -126,6 +128,7 @@ hipError_t launch_stream_read(const void *data, uint64_t n, uint32_t *out, uint3
 uint32_t scan_lds_bytes(int cfg, uint32_t img_cap);
 hipError_t launch_scan(int cfg, int fam, const ScanParams &p, uint32_t grid, uint32_t lds_bytes, hipStream_t s);
 hipError_t scan_occupancy(int cfg, int fam, uint32_t lds_bytes, int *blocks_per_cu);
+hipError_t list_scan(int cfg, int fam, const ListParams *p, uint32_t grid, hipStream_t s, int *blocks_per_cu);
 uint64_t scan_tmp_words(uint64_t n);
 hipError_t launch_exclusive_scan(const uint32_t *in, uint64_t n, uint64_t *out, uint64_t *tmp, uint64_t *total_dev,
                                  hipStream_t s);
