@@ -439,19 +439,32 @@ __device__ __forceinline__ uint32_t screen_key(const uint8_t *end, uint32_t shif
   return h & mask;
 }
 
-// Run of entries (first | count << 16) stored under key, or kNoLink.  The key
-// table is read from the instance image in device memory (gimg).
-__device__ __forceinline__ uint32_t key_lookup(const uint8_t *gimg, const BucketDesc &D, uint64_t key) {
+// Record (slot_inline / slot_run) stored under key in a list bucket's key
+// table, read from the instance image in device memory (gimg); 0 if absent.
+__device__ __forceinline__ uint64_t key_lookup(const uint8_t *gimg, const BucketDesc &D, uint64_t key) {
   const uint64_t *keys = (const uint64_t *)(gimg + D.ht_off);
-  const uint32_t *runs = (const uint32_t *)(gimg + D.ht_off + 8u * (D.ht_mask + 1u));
+  const uint64_t *recs = keys + (D.ht_mask + 1u);
   uint32_t slot = ht_slot(key, D.ht_mask);
   for (uint32_t probe = 0; probe <= D.ht_mask; ++probe) {
     const uint64_t k = keys[slot];
-    if (k == key) return runs[slot];
-    if (k == kEmptyKey) return kNoLink;
+    if (k == key) return recs[slot];
+    if (k == kEmptyKey) return 0;
     slot = (slot + 1u) & D.ht_mask;
   }
-  return kNoLink;
+  return 0;
+}
+
+// Record of the 32-bit key h of a table bucket: the cuckoo slot holding h
+// (LDS) indexes the per-slot records in device memory; 0 if h is no key.
+__device__ __forceinline__ uint64_t table_record(const uint8_t *img, const uint8_t *gimg, const BucketDesc &D,
+                                                 uint32_t h) {
+  const uint32_t *tab = (const uint32_t *)(img + D.fp_off);
+  uint32_t s = ck_slot1(h, D.fp_mask);
+  if (tab[s] != h) {
+    s = ck_slot2(h, D.fp_mask);
+    if (tab[s] != h) return 0;
+  }
+  return ((const uint64_t *)(gimg + D.ht_off))[s];
 }
 
 // Compares the m bytes ending at *end (LDS tile, any alignment) with the
@@ -473,19 +486,24 @@ __device__ __forceinline__ bool window_equals(const uint8_t *end, const uint8_t 
   return true;
 }
 
-// Verifies the run of entries found for the candidate window ending at *end
-// (global end index e): an entry matches when its window starts inside the
-// text and its bytes equal the window's (the byte comparison of Sec. 3.1 that
-// follows every hash hit).  Consecutive entries with the same pattern bytes
-// (identical patterns under several ids) share one comparison.  Returns the
-// number of matching entries; bit i of mask is set for a matching entry i < 32
-// of the run.
-__device__ __forceinline__ uint32_t verify_run(const uint8_t *gimg, const BucketDesc &D, uint32_t run, const uint8_t *end,
+// Verifies the entries of a record (slot_inline / slot_run) for the candidate
+// window ending at *end (global end index e): an entry matches when its window
+// starts inside the text and its bytes equal the window's (the byte comparison
+// of Sec. 3.1 that follows every hash hit).  Consecutive entries with the same
+// pattern bytes (identical patterns under several ids) share one comparison.
+// Returns the number of matching entries; bit i of mask is set for a matching
+// entry i < 32 of the run.
+__device__ __forceinline__ uint32_t verify_run(const uint8_t *gimg, const BucketDesc &D, uint64_t rec, const uint8_t *end,
                                                int64_t e, uint32_t &mask) {
   mask = 0;
-  if (run == kNoLink) return 0;
+  if (rec >> 63) {
+    const uint32_t om = (uint32_t)rec, m = om >> 24;
+    const bool ok = e - (int64_t)m + 1 >= 0 && window_equals(end, gimg + D.pat_off + (om & 0xFFFFFFu), m);
+    mask = ok ? 1u : 0u;
+    return mask;
+  }
   const Entry *ent = (const Entry *)(gimg + D.ent_off);
-  const uint32_t first = run & 0xFFFFu, cnt = run >> 16;
+  const uint32_t first = (uint32_t)rec, cnt = (uint32_t)(rec >> 32);
   uint32_t nh = 0, prev = kNoLink;
   bool prev_ok = false;
   for (uint32_t i = 0; i < cnt; ++i) {
@@ -503,12 +521,35 @@ __device__ __forceinline__ uint32_t verify_run(const uint8_t *gimg, const Bucket
   return nh;
 }
 
-// Entry i of a run matched?  From the mask for i < 32, else compared again.
-__device__ __forceinline__ bool entry_hit(const uint8_t *gimg, const BucketDesc &D, const Entry &en, uint32_t i,
-                                          uint32_t mask, const uint8_t *end, int64_t e) {
-  if (i < 32) return (mask >> i) & 1u;
-  const uint32_t m = en.off_m >> 24;
-  return e - (int64_t)m + 1 >= 0 && window_equals(end, gimg + D.pat_off + (en.off_m & 0xFFFFFFu), m);
+// Writes the matching entries of a verified record as hit records
+// (pid << 40 | start) at slab[o..], up to cap; o advances over all of them.
+__device__ __forceinline__ void write_hits(const uint8_t *gimg, const BucketDesc &D, uint64_t rec, uint32_t mask,
+                                           const uint8_t *end, int64_t e, uint64_t *slab, uint32_t cap, uint32_t &o) {
+  if (rec >> 63) {
+    if (mask) {
+      const uint32_t om = (uint32_t)rec, pid = (uint32_t)(rec >> 32) & 0xFFFFFFu;
+      const uint64_t x = (uint64_t)(e - (int64_t)(om >> 24) + 1);
+      if (o < cap) slab[o] = ((uint64_t)pid << kPosBits) | x;
+      ++o;
+    }
+    return;
+  }
+  const Entry *ent = (const Entry *)(gimg + D.ent_off);
+  const uint32_t first = (uint32_t)rec, cnt = (uint32_t)(rec >> 32);
+  for (uint32_t i = 0; i < cnt; ++i) {
+    const Entry en = ent[first + i];
+    bool hit;
+    if (i < 32) {
+      hit = (mask >> i) & 1u;
+    } else {
+      const uint32_t m = en.off_m >> 24;
+      hit = e - (int64_t)m + 1 >= 0 && window_equals(end, gimg + D.pat_off + (en.off_m & 0xFFFFFFu), m);
+    }
+    if (!hit) continue;
+    const uint64_t x = (uint64_t)(e - (int64_t)(en.off_m >> 24) + 1);
+    if (o < cap) slab[o] = ((uint64_t)en.pid << kPosBits) | x;
+    ++o;
+  }
 }
 
 // ------------------------------------------------------- tile staging (LDS DMA)
@@ -553,15 +594,17 @@ __device__ __forceinline__ void dma_tile(uint8_t *slot, const uint8_t *text, uin
 // candidate mask (window i of the thread at bit word_windows-1-(i%32) of word
 // i/32).  Windows that start before the text or end after it are dropped, the
 // candidates are compacted block-wide into the LDS list in window order, and
-// each is checked by one thread: key recomputed, key table, byte comparison
-// with every pattern chained under the key.  Hits go to the tile's slab (up to
-// cap records) in window order; tile_hits counts them all.  ncand returns the
-// number of candidates (block-uniform).
+// each is checked by one thread: key recomputed, its record (table buckets:
+// the cuckoo slot in the LDS image img; list buckets: the key table in the
+// device image gimg), byte comparison with every pattern of the record.  Hits
+// go to the tile's slab (up to cap records) in window order; tile_hits counts
+// them all.  ncand returns the number of candidates (block-uniform).
 template <int WG, int C>
 __device__ __forceinline__ void candidate_phase(Bits<C> &bits, const BucketDesc &D, const uint8_t *tile, int64_t tstart,
-                                                uint64_t n, int64_t e0, const uint8_t *gimg, uint32_t *cand,
+                                                uint64_t n, int64_t e0, const uint8_t *img, const uint8_t *gimg,
+                                                uint32_t *cand,
                                                 uint32_t *misc, uint64_t *slab, uint32_t cap, uint32_t &tile_hits,
-                                                uint32_t &ncand) {
+                                                uint32_t &ncand, uint64_t rec1 = 0) {
   constexpr uint32_t W = WG * C;
   constexpr int NB = (C + 31) / 32;
   const uint32_t tid = threadIdx.x;
@@ -610,36 +653,61 @@ __device__ __forceinline__ void candidate_phase(Bits<C> &bits, const BucketDesc 
     const uint32_t nc = min(kCandCap, ncand - r0);
     for (uint32_t i0 = 0; i0 < nc; i0 += WG) {
       const uint32_t ci = i0 + tid;
-      uint32_t run = kNoLink, nh = 0, hmask = 0;
+      uint64_t rec = 0;
+      uint32_t nh = 0, hmask = 0;
       const uint8_t *end = nullptr;
       int64_t e = 0;
       const bool screen = D.kind == kListScreen || D.kind == kTableScreen;
+      const bool table = D.kind == kTableScreen || D.kind == kTableExact;
       if (ci < nc) {
         const uint32_t e_rel = cand[ci];
         end = tile + kFront + e_rel;
         e = tstart + (int64_t)e_rel;
-        const uint64_t key = screen ? (uint64_t)screen_key(end, D.shift & 0xFFu, D.mask)
-                                    : horner_exact(end - (m - 1), m);
-        run = key_lookup(gimg, D, key);
-        nh = verify_run(gimg, D, run, end, e, hmask);
+        if (rec1) {
+          rec = rec1;  // the bucket has one key: every candidate's record
+        } else {
+          const uint64_t key = screen ? (uint64_t)screen_key(end, D.shift & 0xFFu, D.mask)
+                                      : horner_exact(end - (m - 1), m);
+          rec = table ? table_record(img, gimg, D, (uint32_t)key) : key_lookup(gimg, D, key);
+        }
+        nh = verify_run(gimg, D, rec, end, e, hmask);
       }
       uint32_t nht;
       const uint32_t hb = block_excl_scan<WG>(nh, misc, nht);
       if (nh) {
         uint32_t o = tile_hits + hb;
-        const Entry *ent = (const Entry *)(gimg + D.ent_off);
-        const uint32_t first = run & 0xFFFFu, cnt = run >> 16;
-        for (uint32_t i = 0; i < cnt; ++i) {
-          const Entry en = ent[first + i];
-          if (!entry_hit(gimg, D, en, i, hmask, end, e)) continue;
-          const uint64_t x = (uint64_t)(e - (int64_t)(en.off_m >> 24) + 1);
-          if (o < cap) slab[o] = ((uint64_t)en.pid << kPosBits) | x;
-          ++o;
-        }
+        write_hits(gimg, D, rec, hmask, end, e, slab, cap, o);
       }
       tile_hits += nht;
     }
   }
+}
+
+// A tile with at least this many candidates in a bucket makes the next tile
+// of the workgroup skip that bucket's test pass (hits are dense: the mask pass
+// runs directly).  Sparse hits (a planted occurrence now and then) keep the
+// cheaper test pass.
+constexpr uint32_t kDenseCand = 32;
+
+// Bucket descriptor b of the LDS image, as wave-uniform values.
+__device__ __forceinline__ BucketDesc read_desc(const uint8_t *img, uint32_t b) {
+  const BucketDesc *dp = (const BucketDesc *)(img + sizeof(ImageHeader) + 64u * b);
+  BucketDesc D;
+  D.m = uni(dp->m);
+  D.kind = uni(dp->kind);
+  D.shift = uni(dp->shift);
+  D.mask = uni(dp->mask);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) D.tgt[j] = uni(dp->tgt[j]);
+  D.fp_off = uni(dp->fp_off);
+  D.fp_mask = uni(dp->fp_mask);
+  D.ht_off = uni(dp->ht_off);
+  D.ht_mask = uni(dp->ht_mask);
+  D.ent_off = uni(dp->ent_off);
+  D.max_m = 0;
+  D.pat_off = uni(dp->pat_off);
+  D.npat = 0;
+  return D;
 }
 
 // ------------------------------------------------------------ the scan kernel
@@ -751,62 +819,59 @@ __global__ __launch_bounds__(WG) void scan_kernel(ScanParams p) {
     const uint32_t nb = uni(H->nbuckets);
     uint32_t tile_hits = 0;
 
-    for (uint32_t b = 0; b < nb; ++b) {
-      const BucketDesc *dp = (const BucketDesc *)(img + sizeof(ImageHeader) + 64u * b);
-      BucketDesc D;
-      D.m = uni(dp->m);
-      D.kind = uni(dp->kind);
-      D.shift = uni(dp->shift);
-      D.mask = uni(dp->mask);
-#pragma unroll
-      for (int j = 0; j < 4; ++j) D.tgt[j] = uni(dp->tgt[j]);
-      D.fp_off = uni(dp->fp_off);
-      D.fp_mask = uni(dp->fp_mask);
-      D.ht_off = uni(dp->ht_off);
-      D.ht_mask = uni(dp->ht_mask);
-      D.ent_off = uni(dp->ent_off);
-      D.max_m = uni(dp->max_m);
-      D.pat_off = uni(dp->pat_off);
-      D.npat = uni(dp->npat);
-      const uint32_t m = D.m;
-      const uint32_t r = (8u * m) % 61u;
-      const uint32_t *fp = (const uint32_t *)(img + D.fp_off);
-      const OutStream os = out_stream(mine, m);
-
-      if constexpr (FAM == kFamExact) {
-        if (D.kind == kDump) {
-          pass_dump<C>(tw, os, m, r, e0, n, p);
+    // Buckets go in chunks of 32: the test pass of every bucket of the chunk
+    // first (one flag bit per bucket and wave), one barrier, then the mask
+    // pass and candidate phase of the buckets whose tile had a candidate.
+    for (uint32_t b0 = 0; b0 < nb; b0 += 32) {
+      const uint32_t nbc = min(32u, nb - b0);
+      uint32_t wave_bits = 0, need = 0;
+      for (uint32_t bi = 0; bi < nbc; ++bi) {
+        const uint32_t b = b0 + bi;
+        const BucketDesc D = read_desc(img, b);
+        const uint32_t m = D.m;
+        const uint32_t r = (8u * m) % 61u;
+        const OutStream os = out_stream(mine, m);
+        if constexpr (FAM == kFamExact) {
+          if (D.kind == kDump) {
+            pass_dump<C>(tw, os, m, r, e0, n, p);
+            continue;
+          }
+        }
+        // skipped while the bucket's previous tile had candidates (dense
+        // hits): the mask pass and its block scan decide then
+        if (b < 32 && ((dense_mask >> b) & 1u)) {
+          need |= 1u << bi;
           continue;
         }
-      }
-
-      // ---- pass 1: wave-level "any candidate" over every window.  Skipped
-      // while the bucket's previous tile had candidates (dense hits): the
-      // mask pass and its block scan decide then.
-      const bool dense = b < 32 && ((dense_mask >> b) & 1u);
-      if (!dense) {
         uint64_t any = 0;
         Bits<C> nob;
-        run_pass<C, true, FAM>(D, tw, os, r, fp, any, nob);
-        uint32_t *flags = misc + 16 + 16 * flag_parity;
-        flag_parity ^= 1u;
-        if (lane == 0) flags[wave] = any != 0;
-        wg_barrier();
-        uint32_t blk_any = 0;
-#pragma unroll
-        for (int i = 0; i < WG / 64; ++i) blk_any |= flags[i];
-        if (!blk_any) continue;
+        run_pass<C, true, FAM>(D, tw, os, r, (const uint32_t *)(img + D.fp_off), any, nob);
+        if (any) wave_bits |= 1u << bi;
       }
-
-      // ---- pass 2 (only when some window of the tile passed): per-thread masks
-      Bits<C> bits;
+      uint32_t *flags = misc + 16 + 16 * flag_parity;
+      flag_parity ^= 1u;
+      if (lane == 0) flags[wave] = wave_bits;
+      wg_barrier();
 #pragma unroll
-      for (int j = 0; j < NB; ++j) bits.b[j] = 0;
-      uint64_t dummy = 0;
-      run_pass<C, false, FAM>(D, tw, os, r, fp, dummy, bits);
-      uint32_t ncand;
-      candidate_phase<WG, C>(bits, D, tile, tstart, n, e0, gimg, cand, misc, slab, cap, tile_hits, ncand);
-      if (b < 32) dense_mask = ncand ? (dense_mask | (1u << b)) : (dense_mask & ~(1u << b));
+      for (int i = 0; i < WG / 64; ++i) need |= flags[i];
+      need = uni(need);
+      while (need) {
+        const uint32_t bi = __builtin_ctz(need);
+        need &= need - 1u;
+        const uint32_t b = b0 + bi;
+        const BucketDesc D = read_desc(img, b);
+        const uint32_t m = D.m;
+        const uint32_t r = (8u * m) % 61u;
+        const OutStream os = out_stream(mine, m);
+        Bits<C> bits;
+#pragma unroll
+        for (int j = 0; j < NB; ++j) bits.b[j] = 0;
+        uint64_t dummy = 0;
+        run_pass<C, false, FAM>(D, tw, os, r, (const uint32_t *)(img + D.fp_off), dummy, bits);
+        uint32_t ncand;
+        candidate_phase<WG, C>(bits, D, tile, tstart, n, e0, img, gimg, cand, misc, slab, cap, tile_hits, ncand);
+        if (b < 32) dense_mask = ncand >= kDenseCand ? (dense_mask | (1u << b)) : (dense_mask & ~(1u << b));
+      }
     }
 
     if (tid == 0 && !p.direct) {
@@ -880,9 +945,9 @@ __global__ __launch_bounds__(WG) void scan_list_kernel(ListParams p) {
       uint64_t dummy = 0;
       run_pass<C, false, FAM>(D, tw, os, r, nullptr, dummy, bits);
       uint32_t ncand;
-      candidate_phase<WG, C>(bits, D, tile, tstart, p.n, e0, p.gimg, cand, misc, p.out + t * (uint64_t)p.slab_cap,
-                             p.slab_cap, tile_hits, ncand);
-      dense = ncand != 0;
+      candidate_phase<WG, C>(bits, D, tile, tstart, p.n, e0, nullptr, p.gimg, cand, misc,
+                             p.out + t * (uint64_t)p.slab_cap, p.slab_cap, tile_hits, ncand, p.rec1);
+      dense = ncand >= kDenseCand;
     }
     if (tid == 0) {
       p.tile_counts[t] = tile_hits;

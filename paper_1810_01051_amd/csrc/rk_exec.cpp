@@ -84,6 +84,20 @@ rk_status plan_build_host(rk_ctx *ctx, const rk_instance *inst, uint32_t count, 
   if (!batch && P->vinsts.size() == 1 && P->vinsts[0].nbuckets == 1) {
     memcpy(&P->list_desc, blob.data() + P->vinsts[0].img_off + sizeof(ImageHeader), sizeof(BucketDesc));
     P->list1 = P->list_desc.kind == kListScreen || P->list_desc.kind == kListExact;
+    if (P->list1) {
+      // a key table holding a single key: its record goes to the kernel directly
+      const uint8_t *img = blob.data() + P->vinsts[0].img_off;
+      const uint32_t S = P->list_desc.ht_mask + 1;
+      const uint64_t *keys = (const uint64_t *)(img + P->list_desc.ht_off);
+      uint32_t used = 0;
+      uint64_t rec = 0;
+      for (uint32_t s = 0; s < S; ++s)
+        if (keys[s] != kEmptyKey) {
+          ++used;
+          rec = keys[S + s];
+        }
+      P->list_rec1 = used == 1 ? rec : 0;
+    }
   }
   P->img_cap = (uint32_t)align_up(P->img_cap, 16);
   if (batch) {
@@ -346,6 +360,7 @@ rk_status count_enqueue(rk_ctx *ctx, const rk_plan *plan, const uint8_t *text, u
     lp.D = plan->list_desc;
     lp.rot = (8u * plan->list_desc.m) % 61u;
     lp.slab_cap = L.S;
+    lp.rec1 = plan->list_rec1;
     lp.tile_counts = p.tile_counts;
     lp.out = p.out;
     lp.total = p.total;

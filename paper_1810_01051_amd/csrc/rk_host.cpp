@@ -164,6 +164,7 @@ static bool build_cuckoo(const std::vector<uint32_t> &keys, uint32_t bits, std::
 struct GroupBody {
   std::vector<uint8_t> lds, glob;
   BucketDesc D;
+  std::vector<uint32_t> tab;  // the cuckoo table (table kinds)
 };
 
 static uint32_t put_bytes(std::vector<uint8_t> &body, const void *p, size_t bytes) {
@@ -178,7 +179,9 @@ static uint32_t put_bytes(std::vector<uint8_t> &body, const void *p, size_t byte
 // address (the caller then splits the group).
 static bool emit_group(const GroupIn &G, GroupBody &out) {
   std::vector<PatRef> P = G.pats;
+  // entries sharing the low key word (the table key) side by side
   std::stable_sort(P.begin(), P.end(), [](const PatRef &a, const PatRef &b) {
+    if ((uint32_t)a.key != (uint32_t)b.key) return (uint32_t)a.key < (uint32_t)b.key;
     if (a.key != b.key) return a.key < b.key;
     if (a.m != b.m) return a.m < b.m;
     const int c = memcmp(a.p, b.p, a.m);  // identical patterns side by side
@@ -233,22 +236,11 @@ static bool emit_group(const GroupIn &G, GroupBody &out) {
     if (!ok) return false;
     D.fp_mask = 32 - bits;  // the kernel's slot shift
     D.fp_off = put_bytes(out.lds, tab.data(), tab.size() * 4);
+    out.tab = std::move(tab);
   }
-  // key -> run of entries (first | count << 16), open addressing
-  const uint32_t S = std::max<uint32_t>(2, next_pow2(2 * (uint32_t)dist.size()));
-  std::vector<uint64_t> keys(S, kEmptyKey);
-  std::vector<uint32_t> vals(S, kNoLink);
+  const bool table = D.kind == kTableScreen || D.kind == kTableExact;
   std::vector<Entry> ents(P.size());
   std::vector<uint8_t> pb;
-  for (size_t i = 0; i < P.size();) {
-    size_t j = i;
-    while (j < P.size() && P[j].key == P[i].key) ++j;
-    uint32_t s = ht_slot(P[i].key, S - 1);
-    while (keys[s] != kEmptyKey) s = (s + 1) & (S - 1);
-    keys[s] = P[i].key;
-    vals[s] = (uint32_t)i | ((uint32_t)(j - i) << 16);
-    i = j;
-  }
   // pattern bytes, each at a 4-byte aligned offset (the kernel compares
   // dwords); identical patterns under several ids are stored once
   uint32_t max_m = 0;
@@ -270,11 +262,41 @@ static bool emit_group(const GroupIn &G, GroupBody &out) {
     ents[i].off_m = off | (P[i].m << 24);  // offset relative to the pattern block
     max_m = std::max(max_m, P[i].m);
   }
-  std::vector<uint8_t> ht(S * 12);
-  memcpy(ht.data(), keys.data(), S * 8);
-  memcpy(ht.data() + S * 8, vals.data(), S * 4);
-  D.ht_mask = S - 1;
-  D.ht_off = put_bytes(out.glob, ht.data(), ht.size());
+  if (table) {
+    // one record per cuckoo slot: the run of entries whose table key sits in
+    // that slot, a single entry held inline
+    const uint32_t S = (uint32_t)out.tab.size(), sh = D.fp_mask;
+    std::vector<uint64_t> rec(S, 0);
+    for (size_t i = 0; i < P.size();) {
+      size_t j = i;
+      while (j < P.size() && (uint32_t)P[j].key == (uint32_t)P[i].key) ++j;
+      const uint32_t h = (uint32_t)P[i].key;
+      uint32_t s = ck_slot1(h, sh);
+      if (out.tab[s] != h) s = ck_slot2(h, sh);
+      rec[s] = (j - i == 1) ? slot_inline(ents[i].pid, ents[i].off_m) : slot_run((uint32_t)i, (uint32_t)(j - i));
+      i = j;
+    }
+    D.ht_mask = S - 1;
+    D.ht_off = put_bytes(out.glob, rec.data(), rec.size() * 8);
+  } else {
+    // key -> run record, open addressing
+    const uint32_t S = std::max<uint32_t>(2, next_pow2(2 * (uint32_t)dist.size()));
+    std::vector<uint64_t> keys(S, kEmptyKey), vals(S, 0);
+    for (size_t i = 0; i < P.size();) {
+      size_t j = i;
+      while (j < P.size() && P[j].key == P[i].key) ++j;
+      uint32_t s = ht_slot(P[i].key, S - 1);
+      while (keys[s] != kEmptyKey) s = (s + 1) & (S - 1);
+      keys[s] = P[i].key;
+      vals[s] = (j - i == 1) ? slot_inline(ents[i].pid, ents[i].off_m) : slot_run((uint32_t)i, (uint32_t)(j - i));
+      i = j;
+    }
+    std::vector<uint8_t> ht(S * 16);
+    memcpy(ht.data(), keys.data(), S * 8);
+    memcpy(ht.data() + S * 8, vals.data(), S * 8);
+    D.ht_mask = S - 1;
+    D.ht_off = put_bytes(out.glob, ht.data(), ht.size());
+  }
   D.ent_off = put_bytes(out.glob, ents.data(), ents.size() * sizeof(Entry));
   D.pat_off = put_bytes(out.glob, pb.data(), pb.size());
   D.max_m = max_m;

@@ -38,8 +38,9 @@ struct BucketDesc {
   uint32_t tgt[4];     // list kinds: targets (padded by repetition)
   uint32_t fp_off;     // table kinds: image offset of the cuckoo table (u32 keys; LDS part)
   uint32_t fp_mask;    // table kinds: 32 - log2(table slots), the slot shift of ck_slot1/2
-  uint32_t ht_off;     // key table: u64 keys[ht_mask+1], then u32 runs[ht_mask+1] (first | count << 16)
-  uint32_t ht_mask;    // key-table slots - 1
+  uint32_t ht_off;     // list kinds: key table, u64 keys[ht_mask+1] then u64 records[ht_mask+1];
+                       // table kinds: u64 records[ht_mask+1], one per cuckoo slot
+  uint32_t ht_mask;    // key-table (list) or cuckoo-table (table) slots - 1
   uint32_t ent_off;    // Entry[npat], sorted by (key, length, pattern id)
   uint32_t max_m;      // longest pattern in the group
   uint32_t pat_off;    // pattern bytes; Entry::off_m low 24 bits are relative to this
@@ -54,6 +55,17 @@ struct Entry {
   uint32_t off_m;  // byte offset of the pattern (bits 0-23) | length << 24
 };
 static_assert(sizeof(Entry) == 16, "entry is 16 bytes");
+
+// Record of a key (list kinds: in the key table; table kinds: per cuckoo
+// slot): the run of entries with that key, or the single entry inline.
+//   bit 63 set : one entry, pattern id in bits 32..55, off_m in bits 0..31
+//   bit 63 clear: count in bits 32..62 (0: no entry), first entry in bits 0..31
+__host__ __device__ inline uint64_t slot_inline(uint32_t pid, uint32_t off_m) {
+  return (1ull << 63) | ((uint64_t)pid << 32) | off_m;
+}
+__host__ __device__ inline uint64_t slot_run(uint32_t first, uint32_t count) {
+  return ((uint64_t)count << 32) | first;
+}
 
 // Slot of a key in a group's key table (the host builds it, the kernel probes it).
 __host__ __device__ inline uint32_t ht_slot(uint64_t key, uint32_t mask) {
@@ -122,6 +134,7 @@ struct ListParams {
   BucketDesc D;               // the bucket (offsets relative to gimg)
   uint32_t rot;               // 8 m mod 61
   uint32_t slab_cap;
+  uint64_t rec1;              // record of the bucket's key if it has exactly one (else 0: look it up)
   uint32_t *tile_counts;
   uint64_t *out;              // slabs [tile][slab_cap]
   unsigned long long *total;

@@ -75,6 +75,7 @@ struct rk_plan {
   uint32_t img_cap = 0;       // LDS bytes reserved for images (max image size)
   bool list1 = false;         // one text, one bucket with register targets: single-bucket kernel
   rk::BucketDesc list_desc;   // that bucket
+  uint64_t list_rec1 = 0;     // its key's record when it has a single key
   uint64_t text_bytes = 0;
   std::vector<rk::RealInst> insts;
   std::vector<rk::VInst> vinsts;

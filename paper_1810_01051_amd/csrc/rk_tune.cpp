@@ -1,7 +1,8 @@
 // Scan-geometry autotuner: times every (workgroup size, windows per thread)
 // entry of the built-in table per mode and pattern length on a synthetic text,
 // checks that every candidate returns the same hits, and keeps the fastest.
-// Ties go to the lower table index.  The table can be saved to and loaded from
+// Times within 2% of the best count as ties, which go to the lower table
+// index (launch-to-launch spread is of that order).  The table can be saved to and loaded from
 // a small JSON file keyed by the device architecture.
 #include <hip/hip_runtime.h>
 
@@ -25,8 +26,10 @@ struct DevBuf {
   hipError_t alloc(size_t b) { return hipMalloc(&p, b ? b : 16); }
 };
 
-// One timed search; returns device ms of count + collect (min over reps) and
-// the sorted hit positions for the cross-check.
+// One candidate geometry: a full search (count + collect) for the hit
+// cross-check, then the scan kernel alone timed with the context's launch
+// events over several counts (the minimum is kept; host round trips between
+// launches do not enter).
 static rk_status time_one(rk_ctx *ctx, int mode, int cfg, const uint8_t *text, uint64_t n,
                           const std::vector<uint8_t> &pat, double *ms, std::vector<uint64_t> *hits) {
   const int saved = ctx->tile_cfg;
@@ -43,35 +46,33 @@ static rk_status time_one(rk_ctx *ctx, int mode, int cfg, const uint8_t *text, u
     rk_plan_destroy(plan);
     return set_err(ctx, RK_ENOMEM, "autotune buffers");
   }
-  hipEvent_t a, b;
-  hipEventCreate(&a);
-  hipEventCreate(&b);
-  double best = 1e30;
   uint64_t total = 0;
-  for (int rep = 0; rep < 4 && st == RK_OK; ++rep) {
-    hipEventRecord(a, nullptr);
-    st = rk_count(ctx, plan, text, n, scratch.p, sb, &total, nullptr);
-    if (st != RK_OK) break;
-    if (!pos.p && pos.alloc(total * 8 + 8) != hipSuccess) {
-      st = set_err(ctx, RK_ENOMEM, "autotune output");
-      break;
-    }
+  st = rk_count(ctx, plan, text, n, scratch.p, sb, &total, nullptr);
+  if (st == RK_OK && pos.alloc(total * 8 + 8) != hipSuccess) st = set_err(ctx, RK_ENOMEM, "autotune output");
+  if (st == RK_OK)
     st = rk_collect(ctx, plan, text, n, scratch.p, sb, nullptr, 0, (uint64_t *)offd.p, (uint64_t *)pos.p, total,
                     nullptr);
-    if (st != RK_OK) break;
-    hipEventRecord(b, nullptr);
-    hipEventSynchronize(b);
-    float t = 0;
-    hipEventElapsedTime(&t, a, b);
-    if (rep > 0) best = std::min(best, (double)t);
-  }
   if (st == RK_OK) {
     hits->resize(total);
-    if (total) hipMemcpy(hits->data(), pos.p, total * 8, hipMemcpyDeviceToHost);
+    if (total && hipMemcpy(hits->data(), pos.p, total * 8, hipMemcpyDeviceToHost) != hipSuccess)
+      st = set_err(ctx, RK_EDEVICE, "autotune readback");
+  }
+  if (st == RK_OK) {
+    const bool prof = ctx->profile;
+    rk_ctx_profile_reset(ctx);
+    ctx->profile = true;
+    for (int rep = 0; rep < 6 && st == RK_OK; ++rep) st = rk_count(ctx, plan, text, n, scratch.p, sb, &total, nullptr);
+    double best = 1e30;
+    for (auto &ev : ctx->prof_events) {
+      if (ev.kind != 0) continue;
+      float t = 0;
+      if (hipEventSynchronize(ev.b) == hipSuccess && hipEventElapsedTime(&t, ev.a, ev.b) == hipSuccess)
+        best = std::min(best, (double)t);
+    }
+    rk_ctx_profile_reset(ctx);
+    ctx->profile = prof;
     *ms = best;
   }
-  hipEventDestroy(a);
-  hipEventDestroy(b);
   rk_plan_destroy(plan);
   return st;
 }
@@ -123,7 +124,7 @@ rk_status tune_run(rk_ctx *ctx, uint64_t n, const uint32_t *lengths, uint32_t nl
       const int md = mode == RK_MODE_EXACT ? 1 : 2;
       std::vector<uint64_t> ref;
       int best = -1;
-      double best_ms = 1e30;
+      double best_ms = 1e30, cfg_ms[kNumTileCfg];
       for (int cfg = 0; cfg < kNumTileCfg; ++cfg) {
         double ms = 0;
         std::vector<uint64_t> hits;
@@ -135,11 +136,11 @@ rk_status tune_run(rk_ctx *ctx, uint64_t n, const uint32_t *lengths, uint32_t nl
         char row[160];
         snprintf(row, sizeof row, "{\"mode\": %d, \"m\": %u, \"cfg\": %d, \"ms\": %.6f}", mode, m, cfg, ms);
         rows.push_back(row);
-        if (ms < best_ms) {
-          best_ms = ms;
-          best = cfg;
-        }
+        cfg_ms[cfg] = ms;
+        best_ms = std::min(best_ms, ms);
       }
+      for (int cfg = kNumTileCfg - 1; cfg >= 0; --cfg)
+        if (cfg_ms[cfg] <= best_ms * 1.02) best = cfg;
       ctx->tune[md][m] = best;
       ctx->tune_measured[md][m] = 1;
     }
