@@ -120,6 +120,33 @@ def run_mode(rk, ctx, text, patterns, mode, steps, warmup):
     return res
 
 
+def stream_read_ceiling(ctx, text, grids=(256, 512, 1024)):
+    """Read bandwidth of the plain streaming kernel (rk_stream_read: every
+    16-byte block of the text read once, no compute) over the same buffer:
+    the practical HBM read ceiling the scan is compared with."""
+    import ctypes
+    import torch
+    from paper_1810_01051_amd import _lib
+    n = text.numel() & ~15
+    best = 0.0
+    for grid in grids:
+        out = torch.empty(grid, dtype=torch.int32, device=text.device)
+        for _ in range(2):
+            ctx.lib.rk_stream_read(ctx.h, ctypes.c_void_p(text.data_ptr()), n, ctypes.c_void_p(out.data_ptr()), grid,
+                                   None)
+        torch.cuda.synchronize()
+        ctx.set_option(_lib.RK_OPT_PROFILE, 1)
+        ctx.profile_reset()
+        for _ in range(5):
+            ctx.lib.rk_stream_read(ctx.h, ctypes.c_void_p(text.data_ptr()), n, ctypes.c_void_p(out.data_ptr()), grid,
+                                   None)
+        k, ms = ctx.profile(4)
+        ctx.set_option(_lib.RK_OPT_PROFILE, 0)
+        ctx.profile_reset()
+        best = max(best, n / (ms / k / 1e3) / 1e9)
+    return round(best, 1)
+
+
 def plan_cfg(ctx, mode):
     m = {"screen": 2, "exact": 1}[mode]
     return ctx.autotune_choice(m, 32)
@@ -523,6 +550,10 @@ def main():
             "hits": r2["total"],
             "same_positions": bool(torch.equal(r2["positions"], res["positions"]))}
         log("%s: %.3f ms/step, scan %.3f ms" % (other, r2["ms_per_step"], r2["scan_ms"]))
+    sr = stream_read_ceiling(ctx, text)
+    line["roofline"]["stream_read_GBps"] = sr
+    line["roofline"]["frac_of_stream_read"] = round(scan_gbs / sr, 4)
+    log("stream-read ceiling %.1f GB/s" % sr)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(s.text, pattern)
         log("cpu baseline %s" % line["cpu_baseline"])
