@@ -712,7 +712,7 @@ __device__ __forceinline__ BucketDesc read_desc(const uint8_t *img, uint32_t b) 
 
 // ------------------------------------------------------------ the scan kernel
 //
-// LDS: [tile: kFront + W + 16][cand: kCandCap u32][misc: 64 u32][image: img_cap]
+// LDS: [slot 0][slot 1][cand: kCandCap u32][misc: 64 u32][image: img_cap]
 template <int WG, int C, int FAM>
 #if RK_WAVES > 0
 __global__ __launch_bounds__(WG, RK_WAVES) void scan_kernel(ScanParams p) {
@@ -1072,42 +1072,47 @@ __global__ __launch_bounds__(256) void compact_slabs(const uint32_t *counts, con
 }
 
 // -------------------------------------------------- stable radix by pattern id
-// Records are pid << 40 | x.  One 8-bit digit of the pid per pass; a block is
-// one wave walking its kRadixBlock records 64 at a time in order, so ranks are
-// stable.
-constexpr int kRadixBlock = 1024;
+// Records are pid << 40 | x.  One DB-bit digit of the pid per pass (8 bits,
+// or 11 when a single 11-bit pass covers every pid); a block is one wave
+// walking its BLK records 64 at a time in order, so ranks are stable.
+constexpr int kRadixBlock = 1024;        // records per block, 8-bit digits
+constexpr int kRadixBlock11 = 8192;      // records per block, 11-bit digits (same histogram size)
 
+template <int DB, int BLK>
 __global__ __launch_bounds__(64) void radix_hist(const uint64_t *in, uint64_t n, uint32_t shift, uint32_t *ghist,
                                                  uint64_t nblk) {
-  __shared__ uint32_t h[256];
-  for (int i = threadIdx.x; i < 256; i += 64) h[i] = 0;
+  constexpr uint32_t ND = 1u << DB;
+  __shared__ uint32_t h[ND];
+  for (uint32_t i = threadIdx.x; i < ND; i += 64) h[i] = 0;
   __syncthreads();
-  const uint64_t base = (uint64_t)blockIdx.x * kRadixBlock;
-  for (int j = 0; j < kRadixBlock; j += 64) {
+  const uint64_t base = (uint64_t)blockIdx.x * BLK;
+  for (int j = 0; j < BLK; j += 64) {
     const uint64_t i = base + j + threadIdx.x;
-    if (i < n) atomicAdd(&h[(in[i] >> shift) & 255u], 1u);
+    if (i < n) atomicAdd(&h[(in[i] >> shift) & (ND - 1u)], 1u);
   }
   __syncthreads();
-  for (int d = threadIdx.x; d < 256; d += 64) ghist[(uint64_t)d * nblk + blockIdx.x] = h[d];
+  for (uint32_t d = threadIdx.x; d < ND; d += 64) ghist[(uint64_t)d * nblk + blockIdx.x] = h[d];
 }
 
+template <int DB, int BLK>
 __global__ __launch_bounds__(64) void radix_scatter(const uint64_t *in, uint64_t n, uint32_t shift,
                                                     const uint64_t *goff, uint64_t nblk, uint64_t *out) {
-  __shared__ uint64_t run[256];
-  for (int d = threadIdx.x; d < 256; d += 64) run[d] = goff[(uint64_t)d * nblk + blockIdx.x];
+  constexpr uint32_t ND = 1u << DB;
+  __shared__ uint64_t run[ND];
+  for (uint32_t d = threadIdx.x; d < ND; d += 64) run[d] = goff[(uint64_t)d * nblk + blockIdx.x];
   __syncthreads();
   const uint32_t lane = threadIdx.x;
   const uint64_t lt_mask = (1ull << lane) - 1ull;
-  const uint64_t base = (uint64_t)blockIdx.x * kRadixBlock;
-  for (int j = 0; j < kRadixBlock; j += 64) {
+  const uint64_t base = (uint64_t)blockIdx.x * BLK;
+  for (int j = 0; j < BLK; j += 64) {
     const uint64_t i = base + j + lane;
     const bool valid = i < n;
     const uint64_t rec = valid ? in[i] : 0;
-    const uint32_t dg = (uint32_t)(rec >> shift) & 255u;
+    const uint32_t dg = (uint32_t)(rec >> shift) & (ND - 1u);
     // lanes holding the same digit
     uint64_t peers = ballot(valid);
 #pragma unroll
-    for (int bit = 0; bit < 8; ++bit) {
+    for (int bit = 0; bit < DB; ++bit) {
       const uint64_t ones = ballot(valid && ((dg >> bit) & 1u));
       peers &= ((dg >> bit) & 1u) ? ones : ~ones;
     }
@@ -1266,18 +1271,34 @@ hipError_t launch_compact(const uint32_t *counts, const uint64_t *offs, uint64_t
 
 uint64_t radix_blocks(uint64_t n) { return (n + kRadixBlock - 1) / kRadixBlock; }
 
-// Stable sort of n records by pid (bits 40.. of each record), npass digits of
-// 8 bits; ping-pongs between a and b; returns the buffer holding the result.
-hipError_t launch_radix(uint64_t *a, uint64_t *b, uint64_t n, uint32_t npass, uint32_t *ghist, uint64_t *goff,
+// Stable sort of n records by pid (bits 40.. of each record) for pids below
+// 2^pid_bits: one 11-bit pass when 8 < pid_bits <= 11, else 8-bit passes.
+// Ping-pongs between a and b; returns the buffer holding the result.  ghist /
+// goff / tmp are sized for 256 * radix_blocks(n) entries, which also covers
+// the 11-bit pass (2048 digits per 8192-record block).
+hipError_t launch_radix(uint64_t *a, uint64_t *b, uint64_t n, uint32_t pid_bits, uint32_t *ghist, uint64_t *goff,
                         uint64_t *tmp, uint64_t **result, hipStream_t s) {
-  const uint64_t nblk = radix_blocks(n);
   uint64_t *src = a, *dst = b;
+  if (n > 0 && pid_bits > 8 && pid_bits <= 11) {
+    const uint64_t nblk = (n + kRadixBlock11 - 1) / kRadixBlock11;
+    hipLaunchKernelGGL((radix_hist<11, kRadixBlock11>), dim3((uint32_t)nblk), dim3(64), 0, s, src, n, kPosBits, ghist,
+                       nblk);
+    hipError_t e = launch_exclusive_scan(ghist, 2048 * nblk, goff, tmp, nullptr, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((radix_scatter<11, kRadixBlock11>), dim3((uint32_t)nblk), dim3(64), 0, s, src, n, kPosBits,
+                       goff, nblk, dst);
+    *result = dst;
+    return hipGetLastError();
+  }
+  const uint64_t nblk = radix_blocks(n);
+  const uint32_t npass = (pid_bits + 7) / 8;
   for (uint32_t ps = 0; ps < npass && n > 0; ++ps) {
     const uint32_t shift = kPosBits + 8 * ps;
-    hipLaunchKernelGGL(radix_hist, dim3((uint32_t)nblk), dim3(64), 0, s, src, n, shift, ghist, nblk);
+    hipLaunchKernelGGL((radix_hist<8, kRadixBlock>), dim3((uint32_t)nblk), dim3(64), 0, s, src, n, shift, ghist, nblk);
     hipError_t e = launch_exclusive_scan(ghist, 256 * nblk, goff, tmp, nullptr, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(radix_scatter, dim3((uint32_t)nblk), dim3(64), 0, s, src, n, shift, goff, nblk, dst);
+    hipLaunchKernelGGL((radix_scatter<8, kRadixBlock>), dim3((uint32_t)nblk), dim3(64), 0, s, src, n, shift, goff,
+                       nblk, dst);
     uint64_t *t = src;
     src = dst;
     dst = t;

@@ -223,11 +223,14 @@ static WorkLayout work_layout(uint64_t total) {
     o = align_up(o + bytes, 256);
     return r;
   };
+  // digit histograms: 256 per 1024-record block (8-bit passes) or 2048 per
+  // 8192-record block (one 11-bit pass), whichever is larger
+  const uint64_t nh = std::max<uint64_t>(256 * w.nblk, 2048 * ((total + 8191) / 8192));
   w.a = take(total * 8);
   w.b = take(total * 8);
-  w.ghist = take(256 * w.nblk * 4);
-  w.goff = take(256 * w.nblk * 8);
-  w.tmp = take(scan_tmp_words(256 * w.nblk) * 8);
+  w.ghist = take(nh * 4);
+  w.goff = take(nh * 8);
+  w.tmp = take(scan_tmp_words(nh) * 8);
   w.total = o;
   return w;
 }
@@ -237,14 +240,11 @@ uint64_t work_bytes_for(const rk_plan *plan, uint64_t total) {
   return work_layout(total).total;
 }
 
-static uint32_t npasses(uint32_t k) {
-  uint32_t p = 0;
-  uint64_t cap = 1;
-  while (cap < k) {
-    cap <<= 8;
-    ++p;
-  }
-  return p;
+// bits of the largest pattern id of k patterns (ids 0..k-1)
+static uint32_t pid_bits(uint32_t k) {
+  uint32_t b = 0;
+  while (b < 32 && (1ull << b) < k) ++b;
+  return b;
 }
 
 static hipError_t prof_begin(rk_ctx *ctx, hipStream_t s, int kind, int *slot) {
@@ -511,7 +511,7 @@ rk_status collect_enqueue_known(rk_ctx *ctx, const rk_plan *plan, uint64_t n, vo
   } else {
     uint8_t *wk = (uint8_t *)work;
     uint64_t *res = nullptr;
-    e = launch_radix((uint64_t *)(wk + WL.a), (uint64_t *)(wk + WL.b), total, npasses(k), (uint32_t *)(wk + WL.ghist),
+    e = launch_radix((uint64_t *)(wk + WL.a), (uint64_t *)(wk + WL.b), total, pid_bits(k), (uint32_t *)(wk + WL.ghist),
                      (uint64_t *)(wk + WL.goff), (uint64_t *)(wk + WL.tmp), &res, s);
     if (e != hipSuccess) return hip_err(ctx, e, "radix sort");
     e = launch_pid_offsets(res, total, k, offsets, s);
