@@ -120,6 +120,19 @@ def run_mode(rk, ctx, text, patterns, mode, steps, warmup):
     return res
 
 
+def make_ctx(rk, args):
+    """Context with the tuning table and any forced geometry / grid."""
+    from paper_1810_01051_amd import _lib
+    ctx = rk.Context(0)
+    if args.tune and os.path.exists(args.tune):
+        ctx.autotune_load(args.tune)
+    if args.cfg >= 0:
+        ctx.set_option(_lib.RK_OPT_TILE_CFG, args.cfg)
+    if args.grid > 0:
+        ctx.set_option(_lib.RK_OPT_GRID, args.grid)
+    return ctx
+
+
 def stream_read_ceiling(ctx, text, grids=(256, 512, 1024)):
     """Read bandwidth of the plain streaming kernel (rk_stream_read: every
     16-byte block of the text read once, no compute) over the same buffer:
@@ -166,9 +179,7 @@ def bench_config3(args):
     s = rkgen.config3()
     log("config3 generated in %.1fs" % (time.perf_counter() - t0))
     text = torch.from_numpy(s.text).to("cuda:0")
-    ctx = rk.Context(0)
-    if args.tune and os.path.exists(args.tune):
-        ctx.autotune_load(args.tune)
+    ctx = make_ctx(rk, args)
     n = text.numel()
     out = {}
     for mode in ("screen", "exact"):
@@ -225,9 +236,7 @@ def bench_config4(args):
         buf[off:off + len(s.text)].copy_(torch.from_numpy(s.text))
     texts = [buf[off:off + len(s.text)] for s, off in zip(insts, offs)]
     torch.cuda.synchronize()
-    ctx = rk.Context(0)
-    if args.tune and os.path.exists(args.tune):
-        ctx.autotune_load(args.tune)
+    ctx = make_ctx(rk, args)
     res = {}
     for mode in ("screen", "exact") if not args.no_exact else ("screen",):
         bp = rk.BatchPlan(ctx, texts, [s.patterns for s in insts], mode)
@@ -316,9 +325,7 @@ def bench_config5(args):
     corpora = [rkgen.config5_corpus(i, n) for i in range(args.corpora)]
     torch.cuda.synchronize()
     log("config5: %d corpora x %d bytes in %.1fs" % (len(corpora), n, time.perf_counter() - t0))
-    ctx = rk.Context(0)
-    if args.tune and os.path.exists(args.tune):
-        ctx.autotune_load(args.tune)
+    ctx = make_ctx(rk, args)
 
     def materialise(specs):
         # gather every sampled (offset, length) on the device, one copy back
@@ -498,14 +505,7 @@ def main():
     log("generated %d bytes in %.1fs" % (args.n, time.perf_counter() - t0))
     text = torch.from_numpy(s.text).to("cuda:0")
     torch.cuda.synchronize()
-    ctx = rk.Context(0)
-    if args.tune and os.path.exists(args.tune):
-        ctx.autotune_load(args.tune)
-    from paper_1810_01051_amd import _lib
-    if args.cfg >= 0:
-        ctx.set_option(_lib.RK_OPT_TILE_CFG, args.cfg)
-    if args.grid > 0:
-        ctx.set_option(_lib.RK_OPT_GRID, args.grid)
+    ctx = make_ctx(rk, args)
 
     res = run_mode(rk, ctx, text, [pattern], args.mode, args.steps, args.warmup)
     log("%s: %.3f ms/step, scan %.3f ms" % (args.mode, res["ms_per_step"], res["scan_ms"]))

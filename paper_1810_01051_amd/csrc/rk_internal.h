@@ -13,7 +13,7 @@ constexpr uint64_t kQ = (1ull << 61) - 1;  // Mersenne modulus 2^61 - 1
 constexpr uint32_t kFront = 64;            // halo bytes kept in front of a tile (>= RK_MAX_M)
 constexpr uint32_t kPosBits = 40;          // hit record = pid << 40 | start position
 constexpr uint64_t kPosMask = (1ull << kPosBits) - 1;
-constexpr uint32_t kCandCap = 1024;        // candidate slots in LDS per workgroup
+constexpr uint32_t kCandCap = 512;         // candidate slots in LDS per workgroup
 constexpr uint32_t kMaxWaves = 16;
 constexpr uint32_t kNoLink = 0xFFFFFFFFu;
 constexpr uint64_t kEmptyKey = ~0ull;      // empty exact-table slot (no canonical hash is >= q)
