@@ -49,11 +49,16 @@ def load_traffic(kernel_tag: str):
     return e
 
 
+# the sources that decide what the scan kernels read and write: the kernels,
+# their descriptors, the table images and the launch geometry
+KERNEL_SOURCES = ("rk_device.hip", "rk_exec.cpp", "rk_host.cpp", "rk_internal.h", "rk_runtime.h")
+
+
 def source_sha() -> str:
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1810_01051_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
+    for f in KERNEL_SOURCES:
         h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -374,21 +379,34 @@ def bench_config5(args):
         stop = threading.Event()
 
         def releaser():
-            i = 0
+            # requests complete out of submission order (a step serves every
+            # waiting request of its corpus), so results are released as they
+            # complete, like a serving client consuming them
+            nxt, open_, done = 0, [], 0
             t_last = time.perf_counter()
-            while i < len(reqs):
+            while True:
+                while nxt < len(reqs) and rids[nxt] is not None:
+                    open_.append(nxt)
+                    nxt += 1
+                if not open_ and (nxt == len(reqs) or stop.is_set()):
+                    return
+                still = []
+                for i in open_:
+                    res = srv.poll(rids[i], fetch=False)
+                    if res is None:
+                        still.append(i)
+                        continue
+                    lat[i] = (res["t_done"] - res["t_submit"], res["status"], int(res["offsets"][-1]))
+                    srv.release(rids[i])
+                    done += 1
+                progressed = len(still) < len(open_)
+                open_ = still
                 if time.perf_counter() - t_last > 5:
                     t_last = time.perf_counter()
-                    log("config5 rate %g: %d/%d requests done" % (rate, i, len(reqs)))
-                if rids[i] is None:
-                    if stop.is_set():
-                        return
-                    time.sleep(0.0002)
-                    continue
-                res = srv.wait(rids[i], timeout=600, fetch=False)
-                lat[i] = (res["t_done"] - res["t_submit"], res["status"], int(res["offsets"][-1]))
-                srv.release(rids[i])
-                i += 1
+                    log("config5 rate %g: %d/%d requests done, %d open (oldest %s)"
+                        % (rate, done, len(reqs), len(open_), open_[0] if open_ else "-"))
+                if not progressed:
+                    time.sleep(0.0005)
 
         th = threading.Thread(target=releaser)
         th.start()

@@ -4,9 +4,11 @@
  * Corpora stay resident in device memory.  Clients submit searches (a corpus
  * id and a pattern set, the problem of Sec. 1 of Shah & Oza: every occurrence
  * of every pattern) from any thread.  A scheduler thread forms steps from the
- * requests that are waiting: per corpus it concatenates their patterns
- * (identical patterns share their bytes in the table image), and a step scans
- * all its corpora in one persistent launch (the batch path of rk.h).  Each
+ * requests that are waiting: a step serves the corpus of the oldest waiting
+ * request together with every other waiting request for that corpus (up to
+ * the step limits and an output estimate), concatenating their patterns
+ * (identical patterns share their bytes in the table image), so that they
+ * share one scan (the batch path of rk.h).  Each
  * step runs count -> admission -> collect: the count pass gives the exact
  * output size, the step is admitted when the output arena can hold it (a
  * step too large for its share of the arena goes back to the queue and is
@@ -35,7 +37,13 @@ typedef struct rk_server rk_server;
 
 typedef struct {
   uint64_t arena_bytes;        /* device memory for hits of steps in flight and of finished,
-                                  unreleased requests (default 4 GiB) */
+                                  unreleased requests (default 4 GiB).  A counted step waits
+                                  until the arena can hold it, so results must be released
+                                  as they are consumed.  Requests complete out of submission
+                                  order (a later request for the oldest request's corpus joins
+                                  its step), so a client that releases only in submission
+                                  order, or waits for every request before releasing any, can
+                                  stall the arena. */
   uint32_t max_inflight;       /* steps in flight on the device, 1..8 (default 2) */
   uint32_t max_step_requests;  /* requests merged into one step (default 4096) */
   uint32_t max_step_patterns;  /* merged patterns per step (default 262144) */

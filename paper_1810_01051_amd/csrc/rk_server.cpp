@@ -2,12 +2,12 @@
 //
 // Client threads append requests to a queue.  One scheduler thread owns a
 // private librk context and up to max_inflight stream slots.  For an idle
-// slot it takes waiting requests in arrival order and concatenates their
-// patterns per corpus, each request's patterns getting consecutive ids of the
-// merged set, so that its result is a contiguous slice of the merged output
-// (no copy per request; identical patterns of one step share their bytes in
-// the table image).  It builds a batch plan with one instance per corpus and
-// enqueues the count pass.  When a slot's count is done the step is admitted
+// slot it takes the oldest waiting request and the other waiting requests for
+// the same corpus, in arrival order, and concatenates their patterns, each
+// request's patterns getting consecutive ids of the merged set, so that its
+// result is a contiguous slice of the merged output (no copy per request;
+// identical patterns of one step share their bytes in the table image).  It
+// builds a batch plan for the corpus and enqueues the count pass.  When a slot's count is done the step is admitted
 // once the output arena can hold its hits; a step that could never fit is
 // split and counted again.  Then the collect pass writes the sorted hits and
 // the per-pattern offsets come back to pinned host memory.  Count and collect
@@ -130,6 +130,7 @@ struct Slot {
   std::vector<Request *> reqs;
   uint64_t step_id = 0, n_total = 0, total = 0, plan_bytes = 0;
   uint32_t ovf = 0;
+  bool estimated = false;              // the step's hit rate entered the server's estimate
   uint64_t pos_off = 0, pos_size = 0;  // merged positions of the step (arena)
   uint64_t aux_off = 0, aux_size = 0;  // per-pattern offsets and sort work (arena)
   double t_start = 0;
@@ -164,6 +165,7 @@ struct rk_server {
   uint64_t submitted = 0, completed = 0, canceled = 0, failed = 0, steps = 0, bytes_scanned = 0;
   uint64_t merged_patterns = 0, request_patterns = 0, admission_waits = 0, step_splits = 0;
   uint32_t step_limit = 0;   // requests per step, lowered after a split and raised again
+  double hits_per_pattern = -1;  // running estimate from counted steps (-1: none yet)
   double busy_s = 0, busy_since = 0;
   uint32_t inflight = 0;
   uint64_t outstanding = 0;  // submitted and not finished
@@ -260,14 +262,34 @@ static rk_status start_step(rk_server *S, Slot &sl, std::unique_lock<std::mutex>
   // take requests in arrival order
   std::vector<Request *> take;
   uint64_t pats = 0;
-  const uint32_t limit = std::min(S->cfg.max_step_requests, std::max<uint32_t>(S->step_limit, 1));
+  // requests are also bounded by the output the step is expected to need:
+  // about 28 bytes per hit (positions, sort buffers, histograms) at the hit
+  // rate per pattern seen so far must fit the slot's share of the arena; the
+  // first step, with no estimate yet, takes a few requests only
+  uint32_t limit = std::min(S->cfg.max_step_requests, std::max<uint32_t>(S->step_limit, 1));
+  if (S->hits_per_pattern < 0) limit = std::min<uint32_t>(limit, 8);
+  const double share = (double)S->arena.cap / (double)S->slots.size();
+  const double per_pat = S->hits_per_pattern < 0 ? 0.0 : 28.0 * S->hits_per_pattern;
+  // A step serves one corpus: the oldest waiting request's, with the other
+  // waiting requests for that corpus in arrival order (requests for other
+  // corpora keep their places).  One corpus per step lets its requests share
+  // the scan and keeps the merged pattern ids (and so the sort) small.
+  const uint32_t corpus = S->pending.front()->corpus;
+  std::deque<Request *> keep;
   while (!S->pending.empty() && take.size() < limit) {
     Request *r = S->pending.front();
-    if (!take.empty() && pats + r->k > S->cfg.max_step_patterns) break;
+    if (r->corpus == corpus) {
+      if (!take.empty() && pats + r->k > S->cfg.max_step_patterns) break;
+      if (!take.empty() && per_pat * (double)(pats + r->k) > share) break;
+      take.push_back(r);
+      pats += r->k;
+    } else {
+      keep.push_back(r);
+    }
     S->pending.pop_front();
-    take.push_back(r);
-    pats += r->k;
   }
+  // the skipped requests go back in front, in their order
+  for (auto it = keep.rbegin(); it != keep.rend(); ++it) S->pending.push_front(*it);
   const uint64_t step_id = S->next_step++;
   const double t0 = now_s();
   for (Request *r : take) {
@@ -363,6 +385,7 @@ static rk_status start_step(rk_server *S, Slot &sl, std::unique_lock<std::mutex>
     return st;
   }
   sl.reqs = take;
+  sl.estimated = false;
   sl.step_id = step_id;
   sl.state = kCounting;
   sl.t_start = t0;
@@ -402,6 +425,11 @@ static bool try_collect(rk_server *S, Slot &sl, std::unique_lock<std::mutex> &lk
   const uint64_t work_b = aup(work_bytes_for(&sl.plan, sl.total), 256);
   const uint64_t need = pos_b + off_b + work_b;
   const uint64_t share = S->arena.cap / S->slots.size();
+  if (k && !sl.estimated) {
+    sl.estimated = true;
+    const double hpp = (double)sl.total / (double)k;
+    S->hits_per_pattern = S->hits_per_pattern < 0 ? hpp : 0.7 * S->hits_per_pattern + 0.3 * hpp;
+  }
   rk_status st = RK_OK;
   if (sl.reqs.size() > 1 && need > share) {
     const uint64_t parts = std::max<uint64_t>(2, (need + share - 1) / std::max<uint64_t>(share, 1));
@@ -581,9 +609,9 @@ rk_status rk_server_create(rk_ctx *ctx, const rk_server_cfg *cfg_in, rk_server *
   }
   // fixed persistent grid: no occupancy query while a stream is being captured
   S->ctx->grid = (uint32_t)S->ctx->num_cu * 4;
-  // staging records per tile: a step may scan every corpus, so the slabs are
-  // kept to a quarter of the text bytes (denser tiles are rescanned)
-  S->ctx->slab_cap = 544;
+  // staging records per tile: the plan default (one per 16 text bytes for
+  // pattern sets), since served requests are hit-dense and a tile whose
+  // records overflow is scanned a second time
   for (int md = 0; md < 3; ++md)
     for (int m = 0; m <= RK_MAX_M; ++m) S->ctx->tune[md][m] = ctx->tune[md][m];
   S->ctx->tile_cfg = ctx->tile_cfg;

@@ -1,6 +1,7 @@
 """GPU parity: librk (through its C ABI) against the CPU oracle, element by
 element, on seeded inputs.  Integer results, so the bar is exact equality."""
 import ctypes
+import os
 
 import numpy as np
 import pytest
@@ -58,8 +59,8 @@ def run(ctx, rk, text_np, pats, mode, opts=None):
 def assert_same(got, ref, label=""):
     go, gp = got
     ro, rp = ref
-    assert go.tolist() == ro.tolist(), "offsets differ %s" % label
-    if gp.tolist() != rp.tolist():
+    assert np.array_equal(go, ro), "offsets differ %s" % label
+    if not np.array_equal(gp, rp):
         lists_g = oracle.split(go, gp)
         lists_r = oracle.split(ro, rp)
         for j, (a, b) in enumerate(zip(lists_g, lists_r)):
@@ -86,6 +87,54 @@ def test_config2_reduced(ctx, rk, mode):
     ref = oracle.search(s.text, s.patterns, threads=4)
     assert int(ref[0][-1]) == 300
     assert_same(got, ref, "config2 " + mode)
+
+
+TUNE = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "profiles", "autotune_gfx950.json")
+THREADS = min(os.cpu_count() or 1, 16)
+
+
+@pytest.fixture(scope="module")
+def bench_ctx(rk):
+    """A context in the launch configuration bench.py times (its tuning table)."""
+    c = rk.Context(0)
+    if os.path.exists(TUNE):
+        c.autotune_load(TUNE)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def config2_full():
+    return rkgen.config2()
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_config2_full_size(bench_ctx, rk, config2_full, mode):
+    """Config 2 at its full size (4 GiB, m=32, 10,000 plants), element by
+    element against the threaded oracle, plus the window hashes of sampled
+    windows against the oracle's direct evaluation."""
+    s = config2_full
+    got = run(bench_ctx, rk, s.text, s.patterns, mode)
+    ref = oracle.search(s.text, s.patterns, threads=THREADS)
+    assert int(ref[0][-1]) == 10000
+    assert_same(got, ref, "config2 full " + mode)
+    if mode == "exact":
+        g = rkgen.rng(2, 99)
+        xs = np.concatenate([g.integers(0, s.text.size - 32, size=2000), s.manifest["plants"][:500]])
+        text = dev(s.text)
+        gh = bench_ctx.window_hashes(text, 32, torch.from_numpy(xs.astype(np.int64))).cpu().numpy()
+        assert gh.astype(np.uint64).tolist() == oracle.window_hashes(s.text, 32, xs).tolist()
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_config3_full_size(bench_ctx, rk, mode):
+    """Config 3 at its full size (1 GiB Zipf text, 1,024 patterns of m=16),
+    element by element against the threaded oracle."""
+    s = rkgen.config3()
+    got = run(bench_ctx, rk, s.text, s.patterns, mode)
+    ref = oracle.search(s.text, s.patterns, threads=THREADS)
+    assert int(ref[0][-1]) > 10 ** 6
+    assert_same(got, ref, "config3 full " + mode)
 
 
 @pytest.mark.parametrize("mode", MODES)

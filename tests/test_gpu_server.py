@@ -126,3 +126,36 @@ def test_cancel_and_errors(ctx, rk, corpora):
     empty = srv.wait(srv.submit(0, []))
     assert empty["status"] == 0 and empty["offsets"].tolist() == [0]
     srv.close()
+
+
+def test_oversized_steps_are_split(ctx, rk, corpora):
+    """A step whose merged output does not fit the arena goes back to the
+    queue and is split; every request still gets its exact result.  The arena
+    holds one request's output and sort work (about 27 bytes per hit) but not
+    two, so any step of two or more requests must be split."""
+    text = corpora[2]
+    h = text.cpu().numpy()
+    # one- and two-byte patterns: each request has many hits, so the fixed
+    # part of a step's need (offsets, radix histograms) is small beside them
+    pats = [h[o:o + m].tobytes() for o, m in ((10, 1), (2000, 1), (40000, 2), (123456, 1))]
+    reqs = [pats[i % 4:] + pats[:i % 4] for i in range(12)]
+    ref = [oracle.search(h, r) for r in reqs]
+    hits = int(ref[0][0][-1])
+    assert hits > 20000
+    srv = rk.Server(ctx, arena_bytes=40 * hits, max_inflight=1, max_step_requests=64)
+    srv.add_corpus(text)
+    rids = [srv.submit(0, r) for r in reqs]
+    # results are released as they are checked: unreleased results hold arena
+    # space that later steps wait for
+    for i, rid in enumerate(rids):
+        res = srv.wait(rid)
+        assert res["status"] == 0, i
+        assert res["offsets"].tolist() == ref[i][0].tolist(), i
+        assert res["positions"].tolist() == ref[i][1].tolist(), i
+        srv.release(rid)
+    srv.drain()
+    st = srv.stats()
+    assert st["completed"] == 12 and st["failed"] == 0
+    # no split means every step held a single request
+    assert st["step_splits"] >= 1 or st["steps"] == 12, st
+    srv.close()
