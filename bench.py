@@ -375,38 +375,29 @@ def bench_config5(args):
         for c in corpora:
             srv.add_corpus(c)
         rids = [None] * len(reqs)
+        index = {}
         lat = {}
         stop = threading.Event()
 
         def releaser():
             # requests complete out of submission order (a step serves every
-            # waiting request of its corpus), so results are released as they
-            # complete, like a serving client consuming them
-            nxt, open_, done = 0, [], 0
+            # waiting request of its corpus): results are taken from the
+            # server's completion queue and released at once, as a serving
+            # client consuming them would
+            done = 0
             t_last = time.perf_counter()
-            while True:
-                while nxt < len(reqs) and rids[nxt] is not None:
-                    open_.append(nxt)
-                    nxt += 1
-                if not open_ and (nxt == len(reqs) or stop.is_set()):
-                    return
-                still = []
-                for i in open_:
-                    res = srv.poll(rids[i], fetch=False)
-                    if res is None:
-                        still.append(i)
-                        continue
-                    lat[i] = (res["t_done"] - res["t_submit"], res["status"], int(res["offsets"][-1]))
-                    srv.release(rids[i])
+            while done < len(reqs) and not stop.is_set():
+                rid = srv.next_done(timeout=5.0)
+                if rid is not None:
+                    while rid not in index:  # the submitting thread records it after submit returns
+                        time.sleep(0.0001)
+                    res = srv.wait(rid, timeout=0.0, fetch=False)
+                    lat[index[rid]] = (res["t_done"] - res["t_submit"], res["status"], int(res["offsets"][-1]))
+                    srv.release(rid)
                     done += 1
-                progressed = len(still) < len(open_)
-                open_ = still
                 if time.perf_counter() - t_last > 5:
                     t_last = time.perf_counter()
-                    log("config5 rate %g: %d/%d requests done, %d open (oldest %s)"
-                        % (rate, done, len(reqs), len(open_), open_[0] if open_ else "-"))
-                if not progressed:
-                    time.sleep(0.0005)
+                    log("config5 rate %g: %d/%d requests done" % (rate, done, len(reqs)))
 
         th = threading.Thread(target=releaser)
         th.start()
@@ -416,6 +407,7 @@ def bench_config5(args):
             if d > 0:
                 time.sleep(d)
             rids[i] = srv.submit(c, pats)
+            index[rids[i]] = i
         t_sub_end = time.perf_counter()
         srv.drain()
         th.join()

@@ -94,6 +94,12 @@ rk_status rk_server_submit(rk_server *srv, uint32_t corpus_id, const uint8_t *by
 rk_status rk_server_poll(rk_server *srv, uint64_t req_id, rk_result_view *out);
 /* Blocks until the request is done or timeout_s passes (RK_EBUSY). */
 rk_status rk_server_wait(rk_server *srv, uint64_t req_id, double timeout_s, rk_result_view *out);
+/* Blocks until a request has finished that no earlier call returned, and
+ * gives its id: requests are reported once each, in the order they finished
+ * (done, canceled or failed), so a client can consume results as they come
+ * and release them at once.  RK_EBUSY if none finishes within timeout_s.  A
+ * request released before it was reported is skipped. */
+rk_status rk_server_next_done(rk_server *srv, double timeout_s, uint64_t *req_id);
 /* Cancels a request that has not been put into a step (RK_EBUSY otherwise). */
 rk_status rk_server_cancel(rk_server *srv, uint64_t req_id);
 /* Copies a finished request's positions (offsets[k] entries) to host memory;

@@ -81,6 +81,7 @@ SIGNATURES = {
     "rk_server_release": (ctypes.c_int, [c_void, ctypes.c_uint64]),
     "rk_server_fetch": (ctypes.c_int, [c_void, ctypes.c_uint64, c_void, ctypes.c_uint64]),
     "rk_server_drain": (ctypes.c_int, [c_void]),
+    "rk_server_next_done": (ctypes.c_int, [c_void, ctypes.c_double, ctypes.POINTER(ctypes.c_uint64)]),
     "rk_server_get_stats": (ctypes.c_int, [c_void, ctypes.POINTER(RkServerStats)]),
     "rk_server_reset_stats": (ctypes.c_int, [c_void]),
     "rk_server_destroy": (None, [c_void]),

@@ -153,11 +153,13 @@ struct rk_server {
   std::condition_variable cv_submit, cv_done;
   std::deque<Request *> pending;
   std::unordered_map<uint64_t, Request *> reqs;
+  std::deque<uint64_t> done_q;  // finished requests in completion order, for rk_server_next_done
   std::vector<Corpus> corpora;
   uint64_t next_id = 1, next_step = 1;
   bool stop = false;
   std::thread th;
   void *arena_dev = nullptr;
+  hipStream_t fetch_stream = nullptr;  // client copies of results (never the legacy stream)
   Arena arena;
   std::vector<Slot> slots;
   // statistics (under mu)
@@ -176,6 +178,7 @@ namespace rk {
 static void finish_request(rk_server *S, Request *r, rk_status st) {
   r->status = st;
   r->t_done = now_s();
+  S->done_q.push_back(r->id);
   if (S->outstanding) --S->outstanding;
   if (st == RK_OK) {
     ++S->completed;
@@ -222,7 +225,9 @@ static void drop_graphs(Slot &sl) {
 template <typename F>
 static rk_status run_maybe_graph(rk_server *S, Slot &sl, hipGraphExec_t *exec, F &&enq) {
   if (!S->cfg.use_graphs) return enq();
-  hipError_t e = hipStreamBeginCapture(sl.stream, hipStreamCaptureModeThreadLocal);
+  // relaxed: client threads keep making their own HIP calls while a step is
+  // captured (the capturing thread makes no unsafe call inside enq)
+  hipError_t e = hipStreamBeginCapture(sl.stream, hipStreamCaptureModeRelaxed);
   if (e != hipSuccess) return hip_err(S->ctx, e, "begin capture");
   rk_status st = enq();
   hipGraph_t g = nullptr;
@@ -624,7 +629,9 @@ rk_status rk_server_create(rk_ctx *ctx, const rk_server_cfg *cfg_in, rk_server *
   S->arena.init(cfg.arena_bytes);
   S->step_limit = cfg.max_step_requests;
   S->slots.resize(cfg.max_inflight);
+  e = hipStreamCreateWithFlags(&S->fetch_stream, hipStreamNonBlocking);
   for (Slot &sl : S->slots) {
+    if (e != hipSuccess) break;
     e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.ev_count, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.ev_collect, hipEventDisableTiming);
@@ -755,7 +762,32 @@ rk_status rk_server_release(rk_server *S, uint64_t id) {
   }
   delete r;
   S->reqs.erase(it);
+  // ids released before rk_server_next_done reported them are dropped from
+  // the completion queue once they outnumber the live requests
+  if (S->done_q.size() > 2 * S->reqs.size() + 1024) {
+    std::deque<uint64_t> keep;
+    for (uint64_t d : S->done_q)
+      if (S->reqs.count(d)) keep.push_back(d);
+    S->done_q.swap(keep);
+  }
   return RK_OK;
+}
+
+rk_status rk_server_next_done(rk_server *S, double timeout_s, uint64_t *req_id) {
+  if (!S || !req_id) return RK_EINVAL;
+  std::unique_lock<std::mutex> lk(S->mu);
+  const auto until = std::chrono::steady_clock::now() + std::chrono::duration<double>(timeout_s);
+  for (;;) {
+    while (!S->done_q.empty()) {
+      const uint64_t id = S->done_q.front();
+      S->done_q.pop_front();
+      if (S->reqs.count(id)) {
+        *req_id = id;
+        return RK_OK;
+      }
+    }
+    if (S->cv_done.wait_until(lk, until) == std::cv_status::timeout && S->done_q.empty()) return RK_EBUSY;
+  }
 }
 
 rk_status rk_server_fetch(rk_server *S, uint64_t id, uint64_t *positions_host, uint64_t cap) {
@@ -775,10 +807,13 @@ rk_status rk_server_fetch(rk_server *S, uint64_t id, uint64_t *positions_host, u
   if (bytes && !positions_host) return RK_EINVAL;
   if (!bytes) return RK_OK;
   hipSetDevice(S->device);
-  // the slice stays allocated until rk_server_release (the caller's)
-  return hipMemcpy(positions_host, (uint8_t *)S->arena_dev + off, bytes, hipMemcpyDeviceToHost) == hipSuccess
-             ? RK_OK
-             : RK_EDEVICE;
+  // the slice stays allocated until rk_server_release (the caller's); the copy
+  // runs on the server's own non-blocking stream, so that it neither waits for
+  // nor conflicts with steps being captured or run on the slot streams
+  hipError_t e = hipMemcpyAsync(positions_host, (uint8_t *)S->arena_dev + off, bytes, hipMemcpyDeviceToHost,
+                                S->fetch_stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(S->fetch_stream);
+  return e == hipSuccess ? RK_OK : RK_EDEVICE;
 }
 
 rk_status rk_server_drain(rk_server *S) {
@@ -857,6 +892,7 @@ void rk_server_destroy(rk_server *S) {
     if (sl.hres) hipHostFree(sl.hres);
     if (sl.hctr) hipHostFree(sl.hctr);
   }
+  if (S->fetch_stream) hipStreamDestroy(S->fetch_stream);
   if (S->arena_dev) hipFree(S->arena_dev);
   for (auto &kv : S->reqs) {
     Request *r = kv.second;

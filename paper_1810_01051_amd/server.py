@@ -92,6 +92,16 @@ class Server:
         check(st, None, "rk_server_wait")
         return self._view_to_result(rid, v, fetch)
 
+    def next_done(self, timeout: float = 60.0):
+        """Id of the next finished request, in completion order (each once);
+        None if none finishes within timeout."""
+        rid = ctypes.c_uint64()
+        st = self.lib.rk_server_next_done(self.h, float(timeout), ctypes.byref(rid))
+        if st == _lib.RK_EBUSY:
+            return None
+        check(st, None, "rk_server_next_done")
+        return int(rid.value)
+
     def cancel(self, rid: int) -> int:
         return int(self.lib.rk_server_cancel(self.h, int(rid)))
 

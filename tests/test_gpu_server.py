@@ -159,3 +159,38 @@ def test_oversized_steps_are_split(ctx, rk, corpora):
     # no split means every step held a single request
     assert st["step_splits"] >= 1 or st["steps"] == 12, st
     srv.close()
+
+
+def test_completion_queue(ctx, rk, corpora):
+    """next_done reports every finished request once (done or canceled), in
+    completion order; results consumed and released that way equal solo
+    searches."""
+    reqs, host = make_requests(corpora, 40, seed=11)
+    srv = rk.Server(ctx, arena_bytes=1 << 27, max_inflight=2, max_step_requests=6)
+    for c in corpora:
+        srv.add_corpus(c)
+    rids = [srv.submit(r.corpus, r.patterns) for r in reqs]
+    canceled = {r for r in rids[-6:] if srv.cancel(r) == 0}
+    seen, done_times, got = [], [], {}
+    while len(seen) < len(rids):
+        rid = srv.next_done(timeout=60.0)
+        assert rid is not None, "no completion within 60 s"
+        seen.append(rid)
+        res = srv.wait(rid, timeout=0.0)
+        if rid in canceled:
+            assert res["status"] == rk._lib.RK_ECANCELED
+        else:
+            assert res["status"] == 0
+            done_times.append(res["t_done"])
+            got[rid] = (res["offsets"].tolist(), res["positions"].tolist())
+        srv.release(rid)
+    assert sorted(seen) == sorted(rids)
+    assert done_times == sorted(done_times)
+    assert srv.next_done(timeout=0.05) is None
+    srv.close()
+    for i, rid in enumerate(rids):
+        if rid in canceled:
+            continue
+        r = reqs[i]
+        so, sp = solo(ctx, rk, corpora[r.corpus], r.patterns, "screen")
+        assert got[rid] == (so.tolist(), sp.tolist()), i
