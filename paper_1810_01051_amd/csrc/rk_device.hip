@@ -114,19 +114,248 @@ __device__ __forceinline__ void put_bit(Bits<C> &bits, uint32_t &acc, int i, boo
 
 typedef __attribute__((address_space(3))) const uint32_t lds_word;
 
-// The thread's bytes, loaded from the LDS tile by each pass itself.  The
-// address goes through an empty asm first, so the compiler cannot share the
-// loads (nor the byte extractions that follow them) between the test variants
-// of a bucket and hoist them above the variant switch, which would keep every
-// extracted byte of every variant live at once; no register copy of the words
-// stays live across buckets either.
+// ---------------------------------------------------- LDS reads out of sight
+// The tile pipeline issues the next tiles' loads-to-LDS before testing the
+// current tile.  The compiler cannot tell that the current tile's LDS words
+// are not the ones those loads write, so before any LDS read it can see it
+// waits for every outstanding load -- the next tiles' included, which would
+// end the overlap.  The tile words are therefore read by inline asm (pairs of
+// dwords, then one wait for all of them inside the same statement, so that no
+// word is used before it has arrived; the outputs are early-clobber, as the
+// address is still read after the first word is written); the explicit
+// barriers of the pipeline order these reads after the tile has landed.
+typedef uint32_t rk_u32x2 __attribute__((ext_vector_type(2)));
+
+#define RK_DSP1 "ds_read2_b32 %0, %[a] offset0:0 offset1:1\n"
+#define RK_DSP2 RK_DSP1 "ds_read2_b32 %1, %[a] offset0:2 offset1:3\n"
+#define RK_DSP3 RK_DSP2 "ds_read2_b32 %2, %[a] offset0:4 offset1:5\n"
+#define RK_DSP4 RK_DSP3 "ds_read2_b32 %3, %[a] offset0:6 offset1:7\n"
+#define RK_DSP5 RK_DSP4 "ds_read2_b32 %4, %[a] offset0:8 offset1:9\n"
+#define RK_DSP6 RK_DSP5 "ds_read2_b32 %5, %[a] offset0:10 offset1:11\n"
+#define RK_DSP7 RK_DSP6 "ds_read2_b32 %6, %[a] offset0:12 offset1:13\n"
+#define RK_DSP8 RK_DSP7 "ds_read2_b32 %7, %[a] offset0:14 offset1:15\n"
+#define RK_DSP9 RK_DSP8 "ds_read2_b32 %8, %[a] offset0:16 offset1:17\n"
+#define RK_DSP10 RK_DSP9 "ds_read2_b32 %9, %[a] offset0:18 offset1:19\n"
+#define RK_DSP11 RK_DSP10 "ds_read2_b32 %10, %[a] offset0:20 offset1:21\n"
+#define RK_DSP12 RK_DSP11 "ds_read2_b32 %11, %[a] offset0:22 offset1:23\n"
+#define RK_DSP13 RK_DSP12 "ds_read2_b32 %12, %[a] offset0:24 offset1:25\n"
+#define RK_DSP14 RK_DSP13 "ds_read2_b32 %13, %[a] offset0:26 offset1:27\n"
+#define RK_DSP15 RK_DSP14 "ds_read2_b32 %14, %[a] offset0:28 offset1:29\n"
+#define RK_DSP16 RK_DSP15 "ds_read2_b32 %15, %[a] offset0:30 offset1:31\n"
+#define RK_DSP17 RK_DSP16 "ds_read2_b32 %16, %[a] offset0:32 offset1:33\n"
+#define RK_DSP18 RK_DSP17 "ds_read2_b32 %17, %[a] offset0:34 offset1:35\n"
+#define RK_DSP19 RK_DSP18 "ds_read2_b32 %18, %[a] offset0:36 offset1:37\n"
+#define RK_DSP20 RK_DSP19 "ds_read2_b32 %19, %[a] offset0:38 offset1:39\n"
+#define RK_DSP21 RK_DSP20 "ds_read2_b32 %20, %[a] offset0:40 offset1:41\n"
+#define RK_DSP22 RK_DSP21 "ds_read2_b32 %21, %[a] offset0:42 offset1:43\n"
+#define RK_DSP23 RK_DSP22 "ds_read2_b32 %22, %[a] offset0:44 offset1:45\n"
+#define RK_DSP24 RK_DSP23 "ds_read2_b32 %23, %[a] offset0:46 offset1:47\n"
+#define RK_DSO1(v) "=&v"(v[0])
+#define RK_DSO2(v) RK_DSO1(v), "=&v"(v[1])
+#define RK_DSO3(v) RK_DSO2(v), "=&v"(v[2])
+#define RK_DSO4(v) RK_DSO3(v), "=&v"(v[3])
+#define RK_DSO5(v) RK_DSO4(v), "=&v"(v[4])
+#define RK_DSO6(v) RK_DSO5(v), "=&v"(v[5])
+#define RK_DSO7(v) RK_DSO6(v), "=&v"(v[6])
+#define RK_DSO8(v) RK_DSO7(v), "=&v"(v[7])
+#define RK_DSO9(v) RK_DSO8(v), "=&v"(v[8])
+#define RK_DSO10(v) RK_DSO9(v), "=&v"(v[9])
+#define RK_DSO11(v) RK_DSO10(v), "=&v"(v[10])
+#define RK_DSO12(v) RK_DSO11(v), "=&v"(v[11])
+#define RK_DSO13(v) RK_DSO12(v), "=&v"(v[12])
+#define RK_DSO14(v) RK_DSO13(v), "=&v"(v[13])
+#define RK_DSO15(v) RK_DSO14(v), "=&v"(v[14])
+#define RK_DSO16(v) RK_DSO15(v), "=&v"(v[15])
+#define RK_DSO17(v) RK_DSO16(v), "=&v"(v[16])
+#define RK_DSO18(v) RK_DSO17(v), "=&v"(v[17])
+#define RK_DSO19(v) RK_DSO18(v), "=&v"(v[18])
+#define RK_DSO20(v) RK_DSO19(v), "=&v"(v[19])
+#define RK_DSO21(v) RK_DSO20(v), "=&v"(v[20])
+#define RK_DSO22(v) RK_DSO21(v), "=&v"(v[21])
+#define RK_DSO23(v) RK_DSO22(v), "=&v"(v[22])
+#define RK_DSO24(v) RK_DSO23(v), "=&v"(v[23])
+
+// reads NW consecutive dwords at LDS byte address a (4-byte aligned) into w
+template <int NW>
+__device__ __forceinline__ void lds_read_words(uint32_t *w, uint32_t a) {
+  constexpr int P = NW / 2;
+  static_assert(NW >= 2 && P <= 24, "word count within the generated forms");
+  rk_u32x2 v[P];
+  uint32_t last = 0;
+  (void)last;
+  if constexpr (P == 1) {
+    if constexpr (NW & 1)
+      __asm__ volatile(RK_DSP1 "ds_read_b32 %[l], %[a] offset:%[o]\n\ts_waitcnt lgkmcnt(0)"
+                       : RK_DSO1(v), [l] "=&v"(last) : [a] "v"(a), [o] "n"(8 * P) : "memory");
+    else
+      __asm__ volatile(RK_DSP1 "s_waitcnt lgkmcnt(0)" : RK_DSO1(v) : [a] "v"(a) : "memory");
+  } else if constexpr (P == 2) {
+    if constexpr (NW & 1)
+      __asm__ volatile(RK_DSP2 "ds_read_b32 %[l], %[a] offset:%[o]\n\ts_waitcnt lgkmcnt(0)"
+                       : RK_DSO2(v), [l] "=&v"(last) : [a] "v"(a), [o] "n"(8 * P) : "memory");
+    else
+      __asm__ volatile(RK_DSP2 "s_waitcnt lgkmcnt(0)" : RK_DSO2(v) : [a] "v"(a) : "memory");
+  } else if constexpr (P == 3) {
+    if constexpr (NW & 1)
+      __asm__ volatile(RK_DSP3 "ds_read_b32 %[l], %[a] offset:%[o]\n\ts_waitcnt lgkmcnt(0)"
+                       : RK_DSO3(v), [l] "=&v"(last) : [a] "v"(a), [o] "n"(8 * P) : "memory");
+    else
+      __asm__ volatile(RK_DSP3 "s_waitcnt lgkmcnt(0)" : RK_DSO3(v) : [a] "v"(a) : "memory");
+  } else if constexpr (P == 4) {
+    if constexpr (NW & 1)
+      __asm__ volatile(RK_DSP4 "ds_read_b32 %[l], %[a] offset:%[o]\n\ts_waitcnt lgkmcnt(0)"
+                       : RK_DSO4(v), [l] "=&v"(last) : [a] "v"(a), [o] "n"(8 * P) : "memory");
+    else
+      __asm__ volatile(RK_DSP4 "s_waitcnt lgkmcnt(0)" : RK_DSO4(v) : [a] "v"(a) : "memory");
+  } else if constexpr (P == 5) {
+    if constexpr (NW & 1)
+      __asm__ volatile(RK_DSP5 "ds_read_b32 %[l], %[a] offset:%[o]\n\ts_waitcnt lgkmcnt(0)"
+                       : RK_DSO5(v), [l] "=&v"(last) : [a] "v"(a), [o] "n"(8 * P) : "memory");
+    else
+      __asm__ volatile(RK_DSP5 "s_waitcnt lgkmcnt(0)" : RK_DSO5(v) : [a] "v"(a) : "memory");
+  } else if constexpr (P == 6) {
+    if constexpr (NW & 1)
+      __asm__ volatile(RK_DSP6 "ds_read_b32 %[l], %[a] offset:%[o]\n\ts_waitcnt lgkmcnt(0)"
+                       : RK_DSO6(v), [l] "=&v"(last) : [a] "v"(a), [o] "n"(8 * P) : "memory");
+    else
+      __asm__ volatile(RK_DSP6 "s_waitcnt lgkmcnt(0)" : RK_DSO6(v) : [a] "v"(a) : "memory");
+  } else if constexpr (P == 7) {
+    if constexpr (NW & 1)
+      __asm__ volatile(RK_DSP7 "ds_read_b32 %[l], %[a] offset:%[o]\n\ts_waitcnt lgkmcnt(0)"
+                       : RK_DSO7(v), [l] "=&v"(last) : [a] "v"(a), [o] "n"(8 * P) : "memory");
+    else
+      __asm__ volatile(RK_DSP7 "s_waitcnt lgkmcnt(0)" : RK_DSO7(v) : [a] "v"(a) : "memory");
+  } else if constexpr (P == 8) {
+    if constexpr (NW & 1)
+      __asm__ volatile(RK_DSP8 "ds_read_b32 %[l], %[a] offset:%[o]\n\ts_waitcnt lgkmcnt(0)"
+                       : RK_DSO8(v), [l] "=&v"(last) : [a] "v"(a), [o] "n"(8 * P) : "memory");
+    else
+      __asm__ volatile(RK_DSP8 "s_waitcnt lgkmcnt(0)" : RK_DSO8(v) : [a] "v"(a) : "memory");
+  } else if constexpr (P == 9) {
+    if constexpr (NW & 1)
+      __asm__ volatile(RK_DSP9 "ds_read_b32 %[l], %[a] offset:%[o]\n\ts_waitcnt lgkmcnt(0)"
+                       : RK_DSO9(v), [l] "=&v"(last) : [a] "v"(a), [o] "n"(8 * P) : "memory");
+    else
+      __asm__ volatile(RK_DSP9 "s_waitcnt lgkmcnt(0)" : RK_DSO9(v) : [a] "v"(a) : "memory");
+  } else if constexpr (P == 10) {
+    if constexpr (NW & 1)
+      __asm__ volatile(RK_DSP10 "ds_read_b32 %[l], %[a] offset:%[o]\n\ts_waitcnt lgkmcnt(0)"
+                       : RK_DSO10(v), [l] "=&v"(last) : [a] "v"(a), [o] "n"(8 * P) : "memory");
+    else
+      __asm__ volatile(RK_DSP10 "s_waitcnt lgkmcnt(0)" : RK_DSO10(v) : [a] "v"(a) : "memory");
+  } else if constexpr (P == 11) {
+    if constexpr (NW & 1)
+      __asm__ volatile(RK_DSP11 "ds_read_b32 %[l], %[a] offset:%[o]\n\ts_waitcnt lgkmcnt(0)"
+                       : RK_DSO11(v), [l] "=&v"(last) : [a] "v"(a), [o] "n"(8 * P) : "memory");
+    else
+      __asm__ volatile(RK_DSP11 "s_waitcnt lgkmcnt(0)" : RK_DSO11(v) : [a] "v"(a) : "memory");
+  } else if constexpr (P == 12) {
+    if constexpr (NW & 1)
+      __asm__ volatile(RK_DSP12 "ds_read_b32 %[l], %[a] offset:%[o]\n\ts_waitcnt lgkmcnt(0)"
+                       : RK_DSO12(v), [l] "=&v"(last) : [a] "v"(a), [o] "n"(8 * P) : "memory");
+    else
+      __asm__ volatile(RK_DSP12 "s_waitcnt lgkmcnt(0)" : RK_DSO12(v) : [a] "v"(a) : "memory");
+  } else if constexpr (P == 13) {
+    if constexpr (NW & 1)
+      __asm__ volatile(RK_DSP13 "ds_read_b32 %[l], %[a] offset:%[o]\n\ts_waitcnt lgkmcnt(0)"
+                       : RK_DSO13(v), [l] "=&v"(last) : [a] "v"(a), [o] "n"(8 * P) : "memory");
+    else
+      __asm__ volatile(RK_DSP13 "s_waitcnt lgkmcnt(0)" : RK_DSO13(v) : [a] "v"(a) : "memory");
+  } else if constexpr (P == 14) {
+    if constexpr (NW & 1)
+      __asm__ volatile(RK_DSP14 "ds_read_b32 %[l], %[a] offset:%[o]\n\ts_waitcnt lgkmcnt(0)"
+                       : RK_DSO14(v), [l] "=&v"(last) : [a] "v"(a), [o] "n"(8 * P) : "memory");
+    else
+      __asm__ volatile(RK_DSP14 "s_waitcnt lgkmcnt(0)" : RK_DSO14(v) : [a] "v"(a) : "memory");
+  } else if constexpr (P == 15) {
+    if constexpr (NW & 1)
+      __asm__ volatile(RK_DSP15 "ds_read_b32 %[l], %[a] offset:%[o]\n\ts_waitcnt lgkmcnt(0)"
+                       : RK_DSO15(v), [l] "=&v"(last) : [a] "v"(a), [o] "n"(8 * P) : "memory");
+    else
+      __asm__ volatile(RK_DSP15 "s_waitcnt lgkmcnt(0)" : RK_DSO15(v) : [a] "v"(a) : "memory");
+  } else if constexpr (P == 16) {
+    if constexpr (NW & 1)
+      __asm__ volatile(RK_DSP16 "ds_read_b32 %[l], %[a] offset:%[o]\n\ts_waitcnt lgkmcnt(0)"
+                       : RK_DSO16(v), [l] "=&v"(last) : [a] "v"(a), [o] "n"(8 * P) : "memory");
+    else
+      __asm__ volatile(RK_DSP16 "s_waitcnt lgkmcnt(0)" : RK_DSO16(v) : [a] "v"(a) : "memory");
+  } else if constexpr (P == 17) {
+    if constexpr (NW & 1)
+      __asm__ volatile(RK_DSP17 "ds_read_b32 %[l], %[a] offset:%[o]\n\ts_waitcnt lgkmcnt(0)"
+                       : RK_DSO17(v), [l] "=&v"(last) : [a] "v"(a), [o] "n"(8 * P) : "memory");
+    else
+      __asm__ volatile(RK_DSP17 "s_waitcnt lgkmcnt(0)" : RK_DSO17(v) : [a] "v"(a) : "memory");
+  } else if constexpr (P == 18) {
+    if constexpr (NW & 1)
+      __asm__ volatile(RK_DSP18 "ds_read_b32 %[l], %[a] offset:%[o]\n\ts_waitcnt lgkmcnt(0)"
+                       : RK_DSO18(v), [l] "=&v"(last) : [a] "v"(a), [o] "n"(8 * P) : "memory");
+    else
+      __asm__ volatile(RK_DSP18 "s_waitcnt lgkmcnt(0)" : RK_DSO18(v) : [a] "v"(a) : "memory");
+  } else if constexpr (P == 19) {
+    if constexpr (NW & 1)
+      __asm__ volatile(RK_DSP19 "ds_read_b32 %[l], %[a] offset:%[o]\n\ts_waitcnt lgkmcnt(0)"
+                       : RK_DSO19(v), [l] "=&v"(last) : [a] "v"(a), [o] "n"(8 * P) : "memory");
+    else
+      __asm__ volatile(RK_DSP19 "s_waitcnt lgkmcnt(0)" : RK_DSO19(v) : [a] "v"(a) : "memory");
+  } else if constexpr (P == 20) {
+    if constexpr (NW & 1)
+      __asm__ volatile(RK_DSP20 "ds_read_b32 %[l], %[a] offset:%[o]\n\ts_waitcnt lgkmcnt(0)"
+                       : RK_DSO20(v), [l] "=&v"(last) : [a] "v"(a), [o] "n"(8 * P) : "memory");
+    else
+      __asm__ volatile(RK_DSP20 "s_waitcnt lgkmcnt(0)" : RK_DSO20(v) : [a] "v"(a) : "memory");
+  } else if constexpr (P == 21) {
+    if constexpr (NW & 1)
+      __asm__ volatile(RK_DSP21 "ds_read_b32 %[l], %[a] offset:%[o]\n\ts_waitcnt lgkmcnt(0)"
+                       : RK_DSO21(v), [l] "=&v"(last) : [a] "v"(a), [o] "n"(8 * P) : "memory");
+    else
+      __asm__ volatile(RK_DSP21 "s_waitcnt lgkmcnt(0)" : RK_DSO21(v) : [a] "v"(a) : "memory");
+  } else if constexpr (P == 22) {
+    if constexpr (NW & 1)
+      __asm__ volatile(RK_DSP22 "ds_read_b32 %[l], %[a] offset:%[o]\n\ts_waitcnt lgkmcnt(0)"
+                       : RK_DSO22(v), [l] "=&v"(last) : [a] "v"(a), [o] "n"(8 * P) : "memory");
+    else
+      __asm__ volatile(RK_DSP22 "s_waitcnt lgkmcnt(0)" : RK_DSO22(v) : [a] "v"(a) : "memory");
+  } else if constexpr (P == 23) {
+    if constexpr (NW & 1)
+      __asm__ volatile(RK_DSP23 "ds_read_b32 %[l], %[a] offset:%[o]\n\ts_waitcnt lgkmcnt(0)"
+                       : RK_DSO23(v), [l] "=&v"(last) : [a] "v"(a), [o] "n"(8 * P) : "memory");
+    else
+      __asm__ volatile(RK_DSP23 "s_waitcnt lgkmcnt(0)" : RK_DSO23(v) : [a] "v"(a) : "memory");
+  } else if constexpr (P == 24) {
+    if constexpr (NW & 1)
+      __asm__ volatile(RK_DSP24 "ds_read_b32 %[l], %[a] offset:%[o]\n\ts_waitcnt lgkmcnt(0)"
+                       : RK_DSO24(v), [l] "=&v"(last) : [a] "v"(a), [o] "n"(8 * P) : "memory");
+    else
+      __asm__ volatile(RK_DSP24 "s_waitcnt lgkmcnt(0)" : RK_DSO24(v) : [a] "v"(a) : "memory");
+  }
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    w[2 * j] = v[j].x;
+    w[2 * j + 1] = v[j].y;
+  }
+  if constexpr (NW & 1) w[NW - 1] = last;
+}
+
+__device__ __forceinline__ uint32_t lds_addr(const void *p) { return (uint32_t)(uintptr_t)(lds_word *)p; }
+
+// The thread's bytes, loaded from the LDS tile by each pass itself (so that
+// the loads, and the byte extractions that follow them, are not shared between
+// the test variants of a bucket and hoisted above the variant switch, which
+// would keep every extracted byte of every variant live at once; no register
+// copy of the words stays live across buckets either).
 template <int NW>
 __device__ __forceinline__ void load_words(uint32_t *w, const uint32_t *tw) {
-  lds_word *p = (lds_word *)tw;
-  __asm__ volatile("" : "+v"(p));
-#pragma unroll
-  for (int j = 0; j < NW; ++j) w[j] = p[j];
+  lds_read_words<NW>(w, lds_addr(tw));
 }
+
+// The thread's words of a tile already in registers (the 64 bytes before its
+// first window end and its C bytes; for exact passes also the out-stream
+// dwords), or none (nullptr): then each pass reads them from the LDS tile.
+template <int C>
+struct PreWords {
+  uint32_t w[16 + C / 4];
+  uint32_t d[C / 4 + 1];
+};
 
 // Shift-add hash state after the 64 bytes held in w[0..16), i.e. before the
 // thread's first window end: h = sum_j b[63-j] << (S*j) mod 2^32 (bytes older
@@ -162,10 +391,8 @@ __device__ __forceinline__ void any_or(uint64_t &any, uint64_t b) {
 }
 
 template <int C, int S, int NT, bool ANY>
-__device__ __forceinline__ void pass_list_screen(const uint32_t *tw, uint32_t msk, const uint32_t *tg, uint64_t &any,
-                                                 Bits<C> &bits) {
-  uint32_t w[16 + C / 4];
-  load_words<16 + C / 4>(w, tw);
+__device__ __forceinline__ void pass_list_screen_w(const uint32_t *w, uint32_t msk, const uint32_t *tg, uint64_t &any,
+                                                   Bits<C> &bits) {
   uint32_t h = screen_init<S>(w), acc = 0;
   if (RK_MIN_ACC && ANY && NT == 1) {
     // one target: the minimum of h ^ target over the windows is zero iff
@@ -200,16 +427,28 @@ __device__ __forceinline__ void pass_list_screen(const uint32_t *tw, uint32_t ms
   }
 }
 
+// The words come from registers (pre) or from the LDS tile; each branch
+// passes its own register array, so that no pointer selects between them.
+template <int C, int S, int NT, bool ANY, bool PRE>
+__device__ __forceinline__ void pass_list_screen(const uint32_t *tw, uint32_t msk, const uint32_t *tg, uint64_t &any,
+                                                 Bits<C> &bits, const PreWords<C> *pre) {
+  if constexpr (PRE) {
+    pass_list_screen_w<C, S, NT, ANY>(pre->w, msk, tg, any, bits);
+  } else {
+    uint32_t w[16 + C / 4];
+    load_words<16 + C / 4>(w, tw);
+    pass_list_screen_w<C, S, NT, ANY>(w, msk, tg, any, bits);
+  }
+}
+
 // Set test against a cuckoo table in LDS: the key is in one of its two slots.
 __device__ __forceinline__ bool in_cuckoo(const uint32_t *tab, uint32_t sh, uint32_t h) {
   return (tab[ck_slot1(h, sh)] == h) | (tab[ck_slot2(h, sh)] == h);
 }
 
 template <int C, int S, bool ANY>
-__device__ __forceinline__ void pass_table_screen(const uint32_t *tw, uint32_t msk, const uint32_t *tab, uint32_t sh,
-                                                  uint64_t &any, Bits<C> &bits) {
-  uint32_t w[16 + C / 4];
-  load_words<16 + C / 4>(w, tw);
+__device__ __forceinline__ void pass_table_screen_w(const uint32_t *w, uint32_t msk, const uint32_t *tab, uint32_t sh,
+                                                    uint64_t &any, Bits<C> &bits) {
   uint32_t h = screen_init<S>(w), acc = 0;
 #pragma unroll
   for (int i = 0; i < C; ++i) {
@@ -218,6 +457,18 @@ __device__ __forceinline__ void pass_table_screen(const uint32_t *tw, uint32_t m
     const bool c = in_cuckoo(tab, sh, v);
     if (ANY) any_or(any, ballot(c));
     else put_bit<C>(bits, acc, i, c);
+  }
+}
+
+template <int C, int S, bool ANY, bool PRE>
+__device__ __forceinline__ void pass_table_screen(const uint32_t *tw, uint32_t msk, const uint32_t *tab, uint32_t sh,
+                                                  uint64_t &any, Bits<C> &bits, const PreWords<C> *pre) {
+  if constexpr (PRE) {
+    pass_table_screen_w<C, S, ANY>(pre->w, msk, tab, sh, any, bits);
+  } else {
+    uint32_t w[16 + C / 4];
+    load_words<16 + C / 4>(w, tw);
+    pass_table_screen_w<C, S, ANY>(w, msk, tab, sh, any, bits);
   }
 }
 
@@ -281,16 +532,15 @@ __device__ __forceinline__ OutStream out_stream(const uint8_t *mine, uint32_t m)
 }
 
 template <int C, bool ANY, bool TABLE, int NT, int OUTK>
-__device__ __forceinline__ void pass_exact(const uint32_t *tw, OutStream os, uint32_t m, uint32_t r, const uint32_t *tg,
-                                           const uint32_t *fp, uint32_t sh, uint64_t &any, Bits<C> &bits) {
-  uint32_t w[16 + C / 4];
-  load_words<16 + C / 4>(w, tw);
+__device__ __forceinline__ void pass_exact_w(const uint32_t *w, const uint32_t *d, OutStream os, uint32_t m, uint32_t r,
+                                             const uint32_t *tg, const uint32_t *fp, uint32_t sh, uint64_t &any,
+                                             Bits<C> &bits) {
   uint64_t s = exact_init(w, m);
-  uint32_t dlo = os.d[0], ow = 0, acc = 0;
+  uint32_t dlo = d[0], ow = 0, acc = 0;
 #pragma unroll
   for (int i = 0; i < C; ++i) {
     if ((i & 3) == 0) {
-      const uint32_t dhi = os.d[(i >> 2) + 1];
+      const uint32_t dhi = d[(i >> 2) + 1];
       ow = __builtin_amdgcn_alignbyte(dhi, dlo, os.sh);
       dlo = dhi;
     }
@@ -315,13 +565,28 @@ __device__ __forceinline__ void pass_exact(const uint32_t *tw, OutStream os, uin
   }
 }
 
-template <int C, bool ANY, bool TABLE, int NT>
+template <int C, bool ANY, bool TABLE, int NT, int OUTK, bool PRE>
+__device__ __forceinline__ void pass_exact(const uint32_t *tw, OutStream os, uint32_t m, uint32_t r, const uint32_t *tg,
+                                           const uint32_t *fp, uint32_t sh, uint64_t &any, Bits<C> &bits,
+                                           const PreWords<C> *pre) {
+  if constexpr (PRE) {
+    pass_exact_w<C, ANY, TABLE, NT, OUTK>(pre->w, pre->d, os, m, r, tg, fp, sh, any, bits);
+  } else {
+    uint32_t w[16 + C / 4], d[C / 4 + 1];
+    load_words<16 + C / 4>(w, tw);
+    load_words<C / 4 + 1>(d, os.d);
+    pass_exact_w<C, ANY, TABLE, NT, OUTK>(w, d, os, m, r, tg, fp, sh, any, bits);
+  }
+}
+
+template <int C, bool ANY, bool TABLE, int NT, bool PRE>
 __device__ __forceinline__ void pass_exact_r(const uint32_t *tw, OutStream os, uint32_t m, uint32_t r, const uint32_t *tg,
-                                             const uint32_t *fp, uint32_t sh, uint64_t &any, Bits<C> &bits) {
+                                             const uint32_t *fp, uint32_t sh, uint64_t &any, Bits<C> &bits,
+                                             const PreWords<C> *pre) {
   const int k = out_kind(r);
-  if (k == 0) pass_exact<C, ANY, TABLE, NT, 0>(tw, os, m, r, tg, fp, sh, any, bits);
-  else if (k == 1) pass_exact<C, ANY, TABLE, NT, 1>(tw, os, m, r, tg, fp, sh, any, bits);
-  else pass_exact<C, ANY, TABLE, NT, 2>(tw, os, m, r, tg, fp, sh, any, bits);
+  if (k == 0) pass_exact<C, ANY, TABLE, NT, 0, PRE>(tw, os, m, r, tg, fp, sh, any, bits, pre);
+  else if (k == 1) pass_exact<C, ANY, TABLE, NT, 1, PRE>(tw, os, m, r, tg, fp, sh, any, bits, pre);
+  else pass_exact<C, ANY, TABLE, NT, 2, PRE>(tw, os, m, r, tg, fp, sh, any, bits, pre);
 }
 
 // kDump: canonical rolling hash of windows x = e - m + 1 with x % stride == 0.
@@ -338,11 +603,13 @@ __device__ __forceinline__ void pass_dump(const uint32_t *tw, OutStream os, uint
   if (rem < 0) rem += st;
   // slot of the next sampled window at or after x0 (x0 - rem is a multiple of st)
   int64_t slot = (x0 - rem) / st + (rem ? 1 : 0);
-  uint32_t dlo = os.d[0], ow = 0;
+  uint32_t d[C / 4 + 1];
+  load_words<C / 4 + 1>(d, os.d);
+  uint32_t dlo = d[0], ow = 0;
 #pragma unroll
   for (int i = 0; i < C; ++i) {
     if ((i & 3) == 0) {
-      const uint32_t dhi = os.d[(i >> 2) + 1];
+      const uint32_t dhi = d[(i >> 2) + 1];
       ow = __builtin_amdgcn_alignbyte(dhi, dlo, os.sh);
       dlo = dhi;
     }
@@ -359,41 +626,43 @@ __device__ __forceinline__ void pass_dump(const uint32_t *tw, OutStream os, uint
 // Runs the test pass of bucket D over the thread's windows: ANY=true ORs the
 // wave ballots into any, ANY=false fills the per-thread candidate mask.
 // D.shift holds the screen shift in bits 0-7 and the number of list targets
-// (1, or up to 4 padded by repetition) in bits 8-15.
-template <int C, bool ANY, int FAM>
+// (1, or up to 4 padded by repetition) in bits 8-15.  PRE: the thread's words
+// are already in registers (*pre); else each pass reads them from the tile.
+template <int C, bool ANY, int FAM, bool PRE = false>
 __device__ __forceinline__ void run_pass(const BucketDesc &D, const uint32_t *tw, OutStream os, uint32_t r,
-                                         const uint32_t *fp, uint64_t &any, Bits<C> &bits) {
+                                         const uint32_t *fp, uint64_t &any, Bits<C> &bits,
+                                         const PreWords<C> *pre = nullptr) {
   const uint32_t sh = D.shift & 0xFFu;
   if constexpr (FAM == kFamScreen1) {
-    if (sh == 1) pass_list_screen<C, 1, 1, ANY>(tw, D.mask, D.tgt, any, bits);
-    else if (sh == 2) pass_list_screen<C, 2, 1, ANY>(tw, D.mask, D.tgt, any, bits);
-    else if (sh == 4) pass_list_screen<C, 4, 1, ANY>(tw, D.mask, D.tgt, any, bits);
-    else pass_list_screen<C, 8, 1, ANY>(tw, D.mask, D.tgt, any, bits);
+    if (sh == 1) pass_list_screen<C, 1, 1, ANY, PRE>(tw, D.mask, D.tgt, any, bits, pre);
+    else if (sh == 2) pass_list_screen<C, 2, 1, ANY, PRE>(tw, D.mask, D.tgt, any, bits, pre);
+    else if (sh == 4) pass_list_screen<C, 4, 1, ANY, PRE>(tw, D.mask, D.tgt, any, bits, pre);
+    else pass_list_screen<C, 8, 1, ANY, PRE>(tw, D.mask, D.tgt, any, bits, pre);
   } else if constexpr (FAM == kFamScreen) {
     if (D.kind == kListScreen) {
       if ((D.shift >> 8) == 1u) {
-        if (sh == 1) pass_list_screen<C, 1, 1, ANY>(tw, D.mask, D.tgt, any, bits);
-        else if (sh == 2) pass_list_screen<C, 2, 1, ANY>(tw, D.mask, D.tgt, any, bits);
-        else if (sh == 4) pass_list_screen<C, 4, 1, ANY>(tw, D.mask, D.tgt, any, bits);
-        else pass_list_screen<C, 8, 1, ANY>(tw, D.mask, D.tgt, any, bits);
+        if (sh == 1) pass_list_screen<C, 1, 1, ANY, PRE>(tw, D.mask, D.tgt, any, bits, pre);
+        else if (sh == 2) pass_list_screen<C, 2, 1, ANY, PRE>(tw, D.mask, D.tgt, any, bits, pre);
+        else if (sh == 4) pass_list_screen<C, 4, 1, ANY, PRE>(tw, D.mask, D.tgt, any, bits, pre);
+        else pass_list_screen<C, 8, 1, ANY, PRE>(tw, D.mask, D.tgt, any, bits, pre);
       } else {
-        if (sh == 1) pass_list_screen<C, 1, 4, ANY>(tw, D.mask, D.tgt, any, bits);
-        else if (sh == 2) pass_list_screen<C, 2, 4, ANY>(tw, D.mask, D.tgt, any, bits);
-        else if (sh == 4) pass_list_screen<C, 4, 4, ANY>(tw, D.mask, D.tgt, any, bits);
-        else pass_list_screen<C, 8, 4, ANY>(tw, D.mask, D.tgt, any, bits);
+        if (sh == 1) pass_list_screen<C, 1, 4, ANY, PRE>(tw, D.mask, D.tgt, any, bits, pre);
+        else if (sh == 2) pass_list_screen<C, 2, 4, ANY, PRE>(tw, D.mask, D.tgt, any, bits, pre);
+        else if (sh == 4) pass_list_screen<C, 4, 4, ANY, PRE>(tw, D.mask, D.tgt, any, bits, pre);
+        else pass_list_screen<C, 8, 4, ANY, PRE>(tw, D.mask, D.tgt, any, bits, pre);
       }
     } else {
-      if (sh == 1) pass_table_screen<C, 1, ANY>(tw, D.mask, fp, D.fp_mask, any, bits);
-      else if (sh == 2) pass_table_screen<C, 2, ANY>(tw, D.mask, fp, D.fp_mask, any, bits);
-      else if (sh == 4) pass_table_screen<C, 4, ANY>(tw, D.mask, fp, D.fp_mask, any, bits);
-      else pass_table_screen<C, 8, ANY>(tw, D.mask, fp, D.fp_mask, any, bits);
+      if (sh == 1) pass_table_screen<C, 1, ANY, PRE>(tw, D.mask, fp, D.fp_mask, any, bits, pre);
+      else if (sh == 2) pass_table_screen<C, 2, ANY, PRE>(tw, D.mask, fp, D.fp_mask, any, bits, pre);
+      else if (sh == 4) pass_table_screen<C, 4, ANY, PRE>(tw, D.mask, fp, D.fp_mask, any, bits, pre);
+      else pass_table_screen<C, 8, ANY, PRE>(tw, D.mask, fp, D.fp_mask, any, bits, pre);
     }
   } else {
     if (D.kind == kListExact) {
-      if ((D.shift >> 8) <= 2u) pass_exact_r<C, ANY, false, 2>(tw, os, D.m, r, D.tgt, fp, D.fp_mask, any, bits);
-      else pass_exact_r<C, ANY, false, 4>(tw, os, D.m, r, D.tgt, fp, D.fp_mask, any, bits);
+      if ((D.shift >> 8) <= 2u) pass_exact_r<C, ANY, false, 2, PRE>(tw, os, D.m, r, D.tgt, fp, D.fp_mask, any, bits, pre);
+      else pass_exact_r<C, ANY, false, 4, PRE>(tw, os, D.m, r, D.tgt, fp, D.fp_mask, any, bits, pre);
     } else {
-      pass_exact_r<C, ANY, true, 2>(tw, os, D.m, r, D.tgt, fp, D.fp_mask, any, bits);
+      pass_exact_r<C, ANY, true, 2, PRE>(tw, os, D.m, r, D.tgt, fp, D.fp_mask, any, bits, pre);
     }
   }
 }
@@ -897,6 +1166,11 @@ __global__ __launch_bounds__(WG) void scan_kernel(ScanParams p) {
 // beyond its hash pass.  Count mode only (hits into per-tile slabs); a tile
 // whose slab overflows is rescanned by the general kernel.
 //
+// Tile t+1 loads into the other slot while tile t is tested: the thread's
+// words of tile t are read into registers first (out of the compiler's sight,
+// so that it does not wait for the new loads), then tile t+1's loads are
+// issued, then the test runs on registers only.
+//
 // LDS: [slot 0][slot 1][cand: kCandCap u32][misc: 64 u32]
 template <int WG, int C, int FAM>
 __global__ __launch_bounds__(WG) void scan_list_kernel(ListParams p) {
@@ -919,16 +1193,19 @@ __global__ __launch_bounds__(WG) void scan_list_kernel(ListParams p) {
     wg_barrier_loads();  // tile t has landed; every wave is done with the other slot
     const uint8_t *tile = lds + slot * TILE_LDS;
     const int64_t tstart = (int64_t)(t * W);
-    if (nt < p.ntiles) dma_tile<WG, C>(lds + (slot ^ 1u) * TILE_LDS, p.text, p.n, (int64_t)(nt * W));
     const uint32_t *tw = (const uint32_t *)(tile + kFront + tid * C - 64);
     const OutStream os = out_stream(tile + kFront + tid * C, m);
+    PreWords<C> pre;
+    load_words<16 + C / 4>(pre.w, tw);
+    if constexpr (FAM == kFamExact) load_words<C / 4 + 1>(pre.d, os.d);
+    if (nt < p.ntiles) dma_tile<WG, C>(lds + (slot ^ 1u) * TILE_LDS, p.text, p.n, (int64_t)(nt * W));
     const int64_t e0 = tstart + (int64_t)(tid * C);
     uint32_t tile_hits = 0;
     bool run2 = dense;
     if (!dense) {
       uint64_t any = 0;
       Bits<C> nob;
-      run_pass<C, true, FAM>(D, tw, os, r, nullptr, any, nob);
+      run_pass<C, true, FAM, true>(D, tw, os, r, nullptr, any, nob, &pre);
       uint32_t *flags = misc + 16 + 16 * flag_parity;
       flag_parity ^= 1u;
       if (lane == 0) flags[wave] = any != 0;
@@ -943,7 +1220,7 @@ __global__ __launch_bounds__(WG) void scan_list_kernel(ListParams p) {
 #pragma unroll
       for (int j = 0; j < NB; ++j) bits.b[j] = 0;
       uint64_t dummy = 0;
-      run_pass<C, false, FAM>(D, tw, os, r, nullptr, dummy, bits);
+      run_pass<C, false, FAM, true>(D, tw, os, r, nullptr, dummy, bits, &pre);
       uint32_t ncand;
       candidate_phase<WG, C>(bits, D, tile, tstart, p.n, e0, nullptr, p.gimg, cand, misc,
                              p.out + t * (uint64_t)p.slab_cap, p.slab_cap, tile_hits, ncand, p.rec1);

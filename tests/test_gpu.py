@@ -232,6 +232,38 @@ def test_tile_seams_every_geometry(ctx, rk, mode, cfg):
 
 
 @pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3])
+@pytest.mark.parametrize("grid", [1, 7, 0])
+def test_single_pattern_tile_pipeline(ctx, rk, mode, cfg, grid):
+    """One pattern (the single-bucket kernel) in every geometry: with a small
+    forced grid each workgroup walks many tiles through its LDS slots, so
+    every slot is reused; occurrences sit across tile and thread seams and at
+    both ends of a ragged text."""
+    lib = rk._lib.load()
+    wg, c, tb = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
+    lib.rk_tile_cfg(cfg, ctypes.byref(wg), ctypes.byref(c), ctypes.byref(tb))
+    W, C = tb.value, c.value
+    g = rkgen.rng(53, cfg * 3 + grid % 5)
+    n = 37 * W + 91
+    text = rkgen.iid_text(g, n, rkgen.ACGT)
+    m = (32, 5, 17, 64)[cfg]
+    p = rkgen.ACGT[g.integers(0, 4, size=m)].tobytes()
+    for k in range(38):
+        for d in (-m, -m + 1, -1, 0, 1, C - 1, 3 * C + 2):
+            x = k * W + d
+            if 0 <= x <= n - m:
+                text[x:x + m] = np.frombuffer(p, np.uint8)
+    text[n - m:] = np.frombuffer(p, np.uint8)
+    opts = {rk._lib.RK_OPT_TILE_CFG: cfg}
+    if grid:
+        opts[rk._lib.RK_OPT_GRID] = grid
+    got = run(ctx, rk, text, [p], mode, opts)
+    ref = oracle.search(text, [p])
+    assert int(ref[0][-1]) > 30  # overlapping plants of the long patterns overwrite each other
+    assert_same(got, ref, "cfg %d grid %d" % (cfg, grid))
+
+
+@pytest.mark.parametrize("mode", MODES)
 def test_edge_cases(ctx, rk, mode):
     cases = [
         (b"abcab", [b"ab"]),
