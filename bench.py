@@ -433,13 +433,15 @@ def bench_config5(args):
     results = {}
     for rate in args.rates:
         results["batched_%d" % rate] = run(rate, args.warm5, args.duration5, arena_bytes=args.arena,
-                                           max_inflight=args.inflight, use_graphs=True)
+                                           max_inflight=args.inflight, max_step_patterns=args.step_patterns,
+                                           use_graphs=True)
         log("config5 batched %d: %s" % (rate, results["batched_%d" % rate]))
-    base_rate = min(args.rates)
-    results["one_request_per_launch_%d" % base_rate] = run(base_rate, args.warm5, args.duration5,
-                                                            arena_bytes=args.arena, max_inflight=1,
-                                                            max_step_requests=1, use_graphs=False)
-    log("config5 unbatched: %s" % results["one_request_per_launch_%d" % base_rate])
+    # the baseline: one request per step, one step at a time, plain launches,
+    # on the same request stream at every offered rate
+    for rate in ([] if args.no_unbatched else args.rates):
+        results["one_request_per_launch_%d" % rate] = run(rate, args.warm5, args.duration5, arena_bytes=args.arena,
+                                                          max_inflight=1, max_step_requests=1, use_graphs=False)
+        log("config5 unbatched %d: %s" % (rate, results["one_request_per_launch_%d" % rate]))
     top = results["batched_%d" % max(args.rates)]
     line = {
         "metric": "GB/s text scanned (fraction of HBM peak); batched/served p50/p99 latency",
@@ -474,8 +476,11 @@ def main():
     ap.add_argument("--rates", type=float, nargs="+", default=[500, 2000, 8000], help="config5 offered req/s")
     ap.add_argument("--warm5", type=float, default=1.0)
     ap.add_argument("--duration5", type=float, default=10.0)
-    ap.add_argument("--arena", type=int, default=32 << 30, help="config5 server output arena bytes")
+    ap.add_argument("--arena", type=int, default=64 << 30, help="config5 server output arena bytes")
     ap.add_argument("--inflight", type=int, default=2, help="config5 steps in flight")
+    ap.add_argument("--step-patterns", type=int, default=None,
+                    help="config5 merged patterns per step (default: the library's)")
+    ap.add_argument("--no-unbatched", action="store_true", help="config5: skip the one-request-per-launch runs")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (for PMC byte-counter calibration)")
     args = ap.parse_args()

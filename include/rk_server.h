@@ -46,7 +46,13 @@ typedef struct {
                                   stall the arena. */
   uint32_t max_inflight;       /* steps in flight on the device, 1..8 (default 2) */
   uint32_t max_step_requests;  /* requests merged into one step (default 4096) */
-  uint32_t max_step_patterns;  /* merged patterns per step (default 262144) */
+  uint32_t max_step_patterns;  /* merged patterns per step (default 1024; a request with
+                                  more still forms a step of its own).  Larger steps share
+                                  one scan among more requests but cost more per hit (larger
+                                  tables, more candidates per tile, wider sort keys): on the
+                                  64-corpus Zipf-text workload overloaded at 2,000 req/s,
+                                  steps of 256 / 512 / 1,024 / 2,048 / 262,144 merged
+                                  patterns served 458 / 663 / 808 / 563 / 305 req/s. */
   int mode;                    /* rk_mode of every search */
   int use_graphs;              /* 1: replay captured HIP graphs; 0: plain launches */
 } rk_server_cfg;

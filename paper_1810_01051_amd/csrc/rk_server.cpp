@@ -131,6 +131,7 @@ struct Slot {
   uint64_t step_id = 0, n_total = 0, total = 0, plan_bytes = 0;
   uint32_t ovf = 0;
   bool estimated = false;              // the step's hit rate entered the server's estimate
+  uint32_t slab_cap = 0;               // staging records per tile of the step (0: the default)
   uint64_t pos_off = 0, pos_size = 0;  // merged positions of the step (arena)
   uint64_t aux_off = 0, aux_size = 0;  // per-pattern offsets and sort work (arena)
   double t_start = 0;
@@ -351,6 +352,23 @@ static rk_status start_step(rk_server *S, Slot &sl, std::unique_lock<std::mutex>
     if (regrow) drop_graphs(sl);  // captured addresses changed
     if (e != hipSuccess) st = hip_err(S->ctx, e, "step plan buffers");
   }
+  // Staging records per tile, from the expected hits per tile (a tile with
+  // more is rescanned by the collect pass, a whole extra scan for the dense
+  // outputs of merged steps): four times the expected count, between the
+  // default (tile bytes / 16) and half the tile, with the slabs of a step
+  // kept under 2 GiB.
+  sl.slab_cap = 0;
+  if (st == RK_OK && S->hits_per_pattern > 0 && nbytes > 0) {
+    const uint64_t W = (uint64_t)kTileCfgs[sl.plan.cfg].wg * kTileCfgs[sl.plan.cfg].c;
+    // tiles of the step: every virtual instance (group of buckets sharing an
+    // image) scans the corpus once
+    const uint64_t tiles = (nbytes + W - 1) / W * std::max<uint64_t>(1, sl.plan.vinsts.size());
+    const double per_tile = S->hits_per_pattern * (double)kt / (double)tiles;
+    const uint64_t lo = W / 16, hi = std::min<uint64_t>(W / 2, (2ull << 30) / (8 * tiles));
+    const uint64_t want = aup((uint64_t)(4.0 * per_tile) + 1, 64);
+    if (want > lo && hi > lo) sl.slab_cap = (uint32_t)std::min(want, hi);
+  }
+  S->ctx->slab_cap = sl.slab_cap;
   Layout L;
   if (st == RK_OK) st = make_layout(S->ctx, &sl.plan, 0, L);
   if (st == RK_OK) {
@@ -470,6 +488,7 @@ static bool try_collect(rk_server *S, Slot &sl, std::unique_lock<std::mutex> &lk
     if (e != hipSuccess) st = hip_err(S->ctx, e, "offset staging");
     if (st == RK_OK)
       st = run_maybe_graph(S, sl, &sl.gcollect, [&]() -> rk_status {
+        S->ctx->slab_cap = sl.slab_cap;  // the layout of this step's count pass
         rk_status s2 = collect_enqueue_known(S->ctx, &sl.plan, 0, sl.scratch, sl.scratch_cap, work, work_b, doff,
                                              dpos, std::max<uint64_t>(sl.total, 1), sl.total, sl.ovf, sl.stream);
         if (s2 != RK_OK) return s2;
@@ -588,7 +607,7 @@ void rk_server_cfg_default(rk_server_cfg *cfg) {
   cfg->arena_bytes = 4ull << 30;
   cfg->max_inflight = 2;
   cfg->max_step_requests = 4096;
-  cfg->max_step_patterns = 262144;
+  cfg->max_step_patterns = 1024;
   cfg->mode = RK_MODE_SCREEN;
   cfg->use_graphs = 1;
 }

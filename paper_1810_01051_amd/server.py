@@ -17,16 +17,20 @@ from .search import Context, _mode, check_text, pack_patterns
 
 class Server:
     def __init__(self, ctx: Context, arena_bytes: int = 1 << 30, max_inflight: int = 2,
-                 max_step_requests: int = 4096, max_step_patterns: int = 262144, mode="screen",
+                 max_step_requests: int = None, max_step_patterns: int = None, mode="screen",
                  use_graphs: bool = True):
+        """Step limits left at None keep the library's defaults
+        (rk_server_cfg_default)."""
         self.ctx = ctx
         self.lib = ctx.lib
         cfg = _lib.RkServerCfg()
         self.lib.rk_server_cfg_default(ctypes.byref(cfg))
         cfg.arena_bytes = int(arena_bytes)
         cfg.max_inflight = int(max_inflight)
-        cfg.max_step_requests = int(max_step_requests)
-        cfg.max_step_patterns = int(max_step_patterns)
+        if max_step_requests is not None:
+            cfg.max_step_requests = int(max_step_requests)
+        if max_step_patterns is not None:
+            cfg.max_step_patterns = int(max_step_patterns)
         cfg.mode = _mode(mode)
         cfg.use_graphs = 1 if use_graphs else 0
         h = ctypes.c_void_p()
