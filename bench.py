@@ -549,7 +549,8 @@ def main():
         "config": {"workload": "single pattern over DNA: %d B i.i.d. ACGT text, m=32, 10000 planted" % n,
                    "n": n, "m": 32, "k": 1, "mode": args.mode, "tile_cfg": res["cfg"],
                    "hits": res["total"], "result_check": bool(ok)},
-        "roofline": {"bound": "hbm", "kernel": "scan_kernel (rk_count pass)",
+        "roofline": {"bound": "hbm", "kernel": "scan of the rk_count pass (single-bucket scan_list_kernel, "
+                                               "geometry %d)" % res["cfg"],
                      "achieved": round(scan_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(scan_gbs / HBM_PEAK_GBS, 4),
                      "traffic": traffic["bytes_per_launch"] if traffic else None,
