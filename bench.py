@@ -170,6 +170,73 @@ def plan_cfg(ctx, mode):
     return ctx.autotune_choice(m, 32)
 
 
+# ---------------------------------------------------------------- config 1
+def bench_config1(args):
+    """1 MiB of i.i.d. a..z text, one m=8 pattern copied from the text and
+    planted 100 more times: the latency case (the text sits in the caches, so
+    the figure is the time of one whole search, not an HBM fraction).  Every
+    search is count (with its total readback) + collect, timed on the host
+    around a synchronised call; the oracle checks the result and is timed on
+    one host thread and on the threaded path."""
+    import numpy as np
+    import torch
+    import oracle
+    import rkgen
+    import paper_1810_01051_amd as rk
+
+    s = rkgen.config1()
+    text = torch.from_numpy(s.text).to("cuda:0")
+    n = s.text.size
+    ctx = make_ctx(rk, args)
+    runs = max(200, 10 * args.steps)
+    out = {}
+    # cpu_baseline leg: the oracle timed on one host thread and threaded; its
+    # result is also the reference the GPU result is checked against
+    cpu = {}
+    ref = None
+    for threads in (1, min(os.cpu_count() or 1, 16)):
+        ts = []
+        for _ in range(5):
+            t0 = time.perf_counter()
+            ref = oracle.search(s.text, s.patterns, threads=threads)
+            ts.append(time.perf_counter() - t0)
+        cpu["threads_%d_ms" % threads] = round(float(np.median(ts)) * 1e3, 3)
+    for mode in ("screen", "exact"):
+        plan = rk.Plan(ctx, s.patterns, mode)
+        scratch = plan.scratch(n, text.device)
+        total = plan.count(text, scratch)
+        offsets = torch.empty(2, dtype=torch.int64, device=text.device)
+        positions = torch.empty(max(total, 1), dtype=torch.int64, device=text.device)
+        for _ in range(20):
+            t = plan.count(text, scratch)
+            plan.collect(text, t, scratch, out=(offsets, positions))
+        torch.cuda.synchronize()
+        lat = []
+        for _ in range(runs):
+            t0 = time.perf_counter()
+            t = plan.count(text, scratch)
+            plan.collect(text, t, scratch, out=(offsets, positions))
+            torch.cuda.synchronize()
+            lat.append(time.perf_counter() - t0)
+        ok = (offsets.cpu().numpy().astype(np.uint64).tolist() == ref[0].tolist() and
+              positions[:t].cpu().numpy().astype(np.uint64).tolist() == ref[1].tolist())
+        ls = np.array(lat) * 1e3
+        out[mode] = {"p50_ms": round(float(np.percentile(ls, 50)), 4), "p99_ms": round(float(np.percentile(ls, 99)), 4),
+                     "min_ms": round(float(ls.min()), 4), "runs": runs, "hits": int(t), "oracle_ok": bool(ok)}
+        plan.close()
+        log("config1 %s: %s" % (mode, out[mode]))
+    line = {
+        "metric": "latency of one whole search (count + total readback + collect)",
+        "value": out["screen"]["p50_ms"], "unit": "ms", "n_gpus": 1, "steps": runs, "warmup": 20,
+        "ms_per_step": out["screen"]["p50_ms"], "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u8", "data": "synthetic",
+        "config": {"workload": "single short pattern: %d B i.i.d. a..z text, m=8, 100 planted" % n,
+                   "results": out},
+        "cpu_baseline": {"unit": "ms", "kind": "oracle", "sample": "the whole workload", **cpu},
+    }
+    print(json.dumps(line), flush=True)
+
+
 # ---------------------------------------------------------------- config 3
 def bench_config3(args):
     """1,024 patterns of m=16 (512 sampled, 512 random) over 1 GiB of Zipf
@@ -467,9 +534,9 @@ def main():
     ap.add_argument("--tune", default=os.path.join(ROOT, "profiles", "autotune_gfx950.json"))
     ap.add_argument("--cfg", type=int, default=-1, help="force a scan geometry (rk_tile_cfg index)")
     ap.add_argument("--grid", type=int, default=0, help="force the persistent grid size")
-    ap.add_argument("--workload", default="config2", choices=["config2", "config3", "config4", "config5"],
-                    help="config2 (default): the single-pattern DNA scan; config3: 1,024 patterns over Zipf text; config4: batched uneven "
-                         "instances; config5: serving")
+    ap.add_argument("--workload", default="config2", choices=["config1", "config2", "config3", "config4", "config5"],
+                    help="config2 (default): the single-pattern DNA scan; config1: the 1 MiB latency case; config3: "
+                         "1,024 patterns over Zipf text; config4: batched uneven instances; config5: serving")
     ap.add_argument("--count4", type=int, default=4096, help="config4 instances")
     ap.add_argument("--corpora", type=int, default=64, help="config5 corpora")
     ap.add_argument("--corpus-bytes", type=int, default=1 << 30, help="config5 bytes per corpus")
@@ -504,6 +571,8 @@ def main():
         print(json.dumps({"calib_copy_bytes": 1 << 30, "launches": 3}))
         return
 
+    if args.workload == "config1":
+        return bench_config1(args)
     if args.workload == "config3":
         return bench_config3(args)
     if args.workload == "config4":
