@@ -553,8 +553,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build measures one GPU only (the search shards by text range with an "
-              "(m-1)-byte halo; see DESIGN.md); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: a search over several GPUs splits the text into ranges with an "
+              "(m-1)-byte halo, each range being a one-GPU search like this one; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

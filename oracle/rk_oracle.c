@@ -11,7 +11,7 @@
  *   - the pattern hash hx and the window hash hy are the polynomial
  *         h(s[0..m)) = sum_{i<m} s[i] * d^(m-1-i)   (mod q)
  *     evaluated by Horner's rule h <- h*d + s[i]  (the paper's shift-and-add
- *     form is the case d = 2 with no explicit modulus; this build fixes the
+ *     form is the case d = 2 with no explicit modulus; this oracle takes the
  *     base d and the modulus q as parameters, defaulting to d = 256,
  *     q = 2^61 - 1);
  *   - a window x is reported for pattern P iff hy(x) == hx and the bytes
