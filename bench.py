@@ -262,9 +262,15 @@ def bench_config3(args):
         log("config3 %s: %s" % (mode, out[mode]))
         if mode == "screen":
             first = r
-    # oracle check on a prefix: windows wholly inside the first 64 MiB
+    # cpu_baseline leg: the oracle timed on the first 64 MiB; its result also
+    # checks the GPU result there (windows wholly inside the prefix)
     pre = 64 << 20
-    ro, rp = oracle.search(s.text[:pre], s.patterns, threads=min(os.cpu_count() or 1, 16))
+    threads = min(os.cpu_count() or 1, 16)
+    t0 = time.perf_counter()
+    ro, rp = oracle.search(s.text[:pre], s.patterns, threads=threads)
+    dt = time.perf_counter() - t0
+    cpu = {"value": round(pre / dt / 1e9, 4), "unit": "GB/s", "cores": threads, "kind": "oracle",
+           "sample": "first 64 MiB of the same text (%.1f s)" % dt}
     go = first["offsets"].cpu().numpy().astype(np.int64)
     gp = first["positions"].cpu().numpy().astype(np.int64)
     ok = True
@@ -282,6 +288,7 @@ def bench_config3(args):
         "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
         "config": {"workload": "multi-pattern: %d B Zipf(1.1) word text, 1024 patterns m=16 (512 sampled)" % n,
                    "results": out, "oracle_prefix_64MiB_ok": ok},
+        "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
 
@@ -309,6 +316,19 @@ def bench_config4(args):
     texts = [buf[off:off + len(s.text)] for s, off in zip(insts, offs)]
     torch.cuda.synchronize()
     ctx = make_ctx(rk, args)
+    # cpu_baseline leg: the oracle timed on a sample of the instances (every
+    # len/12-th); its results also check the batched results of both modes
+    sample = list(range(0, len(insts), max(1, len(insts) // 12)))
+    threads = min(os.cpu_count() or 1, 16)
+    t0 = time.perf_counter()
+    refs = {}
+    for i in sample:
+        ro, rp = oracle.search(insts[i].text, insts[i].patterns, threads=threads)
+        refs[i] = oracle.split(ro, rp)
+    dt = time.perf_counter() - t0
+    sample_bytes = sum(len(insts[i].text) for i in sample)
+    cpu = {"value": round(sample_bytes / dt / 1e9, 4), "unit": "GB/s", "cores": threads, "kind": "oracle",
+           "sample": "%d of the %d instances, %d bytes (%.1f s)" % (len(sample), len(insts), sample_bytes, dt)}
     res = {}
     for mode in ("screen", "exact") if not args.no_exact else ("screen",):
         bp = rk.BatchPlan(ctx, texts, [s.patterns for s in insts], mode)
@@ -356,11 +376,9 @@ def bench_config4(args):
                 if not np.array_equal(per[i][j], lists[j]):
                     same = False
         oracle_ok = True
-        for i in range(0, len(insts), max(1, len(insts) // 12)):
-            ro, rp = oracle.search(insts[i].text, insts[i].patterns, threads=8)
-            ref = oracle.split(ro, rp)
+        for i in sample:
             for j in range(len(insts[i].patterns)):
-                if per[i][j].astype(np.uint64).tolist() != ref[j].tolist():
+                if per[i][j].astype(np.uint64).tolist() != refs[i][j].tolist():
                     oracle_ok = False
         for p in plans:
             p.close()
@@ -379,6 +397,7 @@ def bench_config4(args):
                    "instances": len(insts), "text_bytes": total_bytes, "results": res,
                    "speedup_vs_one_launch_per_instance": round(
                        sc["batched"]["GB/s"] / max(sc["one_launch_per_instance"]["GB/s"], 1e-9), 2)},
+        "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
 
