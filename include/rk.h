@@ -94,11 +94,13 @@ const char *rk_status_string(rk_status s);
 /* Options (rk_ctx_set_option).  Values are read when a plan is created or a
  * scan is launched. */
 typedef enum {
-  RK_OPT_SLAB_CAP = 1,  /* per-tile staging slots for hits (0 = default: tile bytes / 64).
-                           Tiles with more hits are rescanned by rk_collect. */
+  RK_OPT_SLAB_CAP = 1,  /* per-tile staging slots for hits (0 = default: tile bytes / 64 for
+                           one pattern, / 16 for pattern sets).  Tiles with more hits are
+                           rescanned by rk_collect. */
   RK_OPT_TILE_CFG = 2,  /* scan geometry index into the built-in table (see rk_tile_cfg);
                            -1 = autotuned / default */
-  RK_OPT_GRID = 3,      /* workgroups of the persistent scan (0 = default: 8 per CU) */
+  RK_OPT_GRID = 3,      /* workgroups of the persistent scan (0 = default: as many as are
+                           resident on every CU at once, from the kernel's occupancy) */
   RK_OPT_PROFILE = 4,   /* 1: time every scan launch with HIP events (rk_ctx_profile) */
   RK_OPT_QUEUE = 5      /* 1: scan pulls tiles from an atomic work queue; 0: static striding;
                            -1 (default): queue for multi-instance plans only */
