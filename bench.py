@@ -550,7 +550,7 @@ def main():
     ap.add_argument("--mode", default="screen", choices=["screen", "exact"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-exact", action="store_true", help="skip the every-window exact-hash measurement")
-    ap.add_argument("--tune", default=os.path.join(ROOT, "profiles", "autotune_gfx950.json"))
+    ap.add_argument("--tune", default=os.path.join(ROOT, "paper_1810_01051_amd", "autotune_gfx950.json"))
     ap.add_argument("--cfg", type=int, default=-1, help="force a scan geometry (rk_tile_cfg index)")
     ap.add_argument("--grid", type=int, default=0, help="force the persistent grid size")
     ap.add_argument("--workload", default="config2", choices=["config1", "config2", "config3", "config4", "config5"],

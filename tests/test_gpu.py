@@ -89,7 +89,8 @@ def test_config2_reduced(ctx, rk, mode):
     assert_same(got, ref, "config2 " + mode)
 
 
-TUNE = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "profiles", "autotune_gfx950.json")
+TUNE = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1810_01051_amd",
+                    "autotune_gfx950.json")
 THREADS = min(os.cpu_count() or 1, 16)
 
 
