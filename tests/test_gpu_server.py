@@ -194,3 +194,30 @@ def test_completion_queue(ctx, rk, corpora):
         r = reqs[i]
         so, sp = solo(ctx, rk, corpora[r.corpus], r.patterns, "screen")
         assert got[rid] == (so.tolist(), sp.tolist()), i
+
+
+def test_dense_steps_size_their_slabs(ctx, rk, corpora):
+    """Merged steps of dense short patterns: once the server has a hit-rate
+    estimate it sizes each step's staging slabs from it (more records per tile
+    than the default), and every result still equals the oracle's, in both
+    modes and with several steps in flight."""
+    text = corpora[3]
+    h = text.cpu().numpy()
+    offs = (7, 333, 4096, 70000, 250000, 600000)
+    reqs = [[h[o:o + m].tobytes() for o, m in zip(offs[i % 3:i % 3 + 4], (1, 2, 1, 3))] for i in range(18)]
+    ref = [oracle.search(h, r) for r in reqs]
+    assert min(int(r[0][-1]) for r in ref) > 10000
+    for mode in ("screen", "exact"):
+        srv = rk.Server(ctx, arena_bytes=1 << 30, max_inflight=3, max_step_requests=3, mode=mode)
+        srv.add_corpus(text)
+        rids = [srv.submit(0, r) for r in reqs]
+        for i, rid in enumerate(rids):
+            res = srv.wait(rid)
+            assert res["status"] == 0, (mode, i)
+            assert res["offsets"].tolist() == ref[i][0].tolist(), (mode, i)
+            assert res["positions"].tolist() == ref[i][1].tolist(), (mode, i)
+            srv.release(rid)
+        st = srv.stats()
+        assert st["completed"] == len(reqs) and st["failed"] == 0
+        assert st["steps"] >= len(reqs) // 3
+        srv.close()
