@@ -10,8 +10,7 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-# RK_LIBRARY may name another build of librk (for A/B runs of build variants)
-LIB_PATH = os.environ.get("RK_LIBRARY") or os.path.join(HERE, "librk.so")
+LIB_PATH = os.path.join(HERE, "librk.so")
 
 RK_OK = 0
 RK_EINVAL = -1

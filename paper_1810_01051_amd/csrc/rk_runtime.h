@@ -125,6 +125,18 @@ void plan_sizes(const std::vector<uint8_t> &blob, const std::vector<InstDesc> &d
 void prepare_scan_kernels();
 hipError_t launch_stream_read(const void *data, uint64_t n, uint32_t *out, uint32_t grid, hipStream_t s);
 
+// Launchers of the scan kernels of one family (kFamScreen1 / kFamScreen /
+// kFamExact) and one geometry CFG of kTileCfgs.  The kernels are defined in
+// rk_scan.h and instantiated in the rk_scan_*.hip translation units (split so
+// that they compile in parallel); every other unit sees these declarations only.
+template <int FAM, int CFG>
+struct ScanGeom {
+  static hipError_t launch(const ScanParams &p, uint32_t grid, uint32_t lds_bytes, hipStream_t s);
+  static hipError_t occupancy(uint32_t lds_bytes, int *blocks);
+  static hipError_t list(const ListParams *p, uint32_t grid, hipStream_t s, int *blocks);
+  static hipError_t prepare();
+};
+
 // device translation unit
 uint32_t scan_lds_bytes(int cfg, uint32_t img_cap);
 hipError_t launch_scan(int cfg, int fam, const ScanParams &p, uint32_t grid, uint32_t lds_bytes, hipStream_t s);
