@@ -51,7 +51,7 @@ def load_traffic(kernel_tag: str):
 
 # the sources that decide what the scan kernels read and write: the kernels,
 # their descriptors, the table images and the launch geometry
-KERNEL_SOURCES = ("rk_device.hip", "rk_exec.cpp", "rk_host.cpp", "rk_internal.h", "rk_runtime.h")
+KERNEL_SOURCES = ("rk_scan.h", "rk_dev.h", "rk_exec.cpp", "rk_host.cpp", "rk_internal.h", "rk_runtime.h")
 
 
 def source_sha() -> str:
@@ -63,33 +63,61 @@ def source_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def cpu_baseline(text_np, pattern: bytes, target_s: float = 10.0):
-    """The oracle as it stands, on the first bytes of the same text, sized for
-    about target_s seconds of work."""
-    import oracle
-    threads = max(1, min(os.cpu_count() or 1, 16))
-    probe = min(len(text_np), 1 << 25)
-    t0 = time.perf_counter()
-    oracle.search(text_np[:probe], [pattern], threads=threads)
-    dt = max(time.perf_counter() - t0, 1e-3)
-    rate = probe / dt
-    sample = int(min(len(text_np), max(probe, rate * target_s)))
-    t0 = time.perf_counter()
-    off, pos = oracle.search(text_np[:sample], [pattern], threads=threads)
-    dt = time.perf_counter() - t0
-    return {"value": round(sample / dt / 1e9, 4), "unit": "GB/s", "cores": threads, "kind": "oracle",
-            "sample": "first %d bytes of the same text (%.1f s, %d hits)" % (sample, dt, int(off[-1])),
-            "cpu_model": cpu_model()}
-
-
-def cpu_model() -> str:
+def host_cpu():
+    """The host's CPU as the bench sees it: logical CPUs of the machine, CPUs
+    this process may run on, the thread count the oracle legs use (this
+    process's share, at most 16 per GPU) and the lscpu model name."""
+    total = os.cpu_count() or 1
     try:
-        for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                return line.split(":", 1)[1].strip()
+        usable = len(os.sched_getaffinity(0))
+    except Exception:
+        usable = total
+    model = "unknown"
+    try:
+        import subprocess
+        out = subprocess.run(["lscpu"], stdout=subprocess.PIPE, stderr=subprocess.DEVNULL, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.strip().startswith("Model name"):
+                model = line.split(":", 1)[1].strip()
+                break
     except Exception:
         pass
-    return "unknown"
+    if model == "unknown":
+        try:
+            for line in open("/proc/cpuinfo"):
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+        except Exception:
+            pass
+    return {"cores_total": total, "cores_usable": usable, "threads": max(1, min(usable, 16)), "cpu_model": model}
+
+
+def oracle_rate(text_np, patterns, threads: int, target_s: float):
+    """The oracle on the first bytes of text_np, sized for about target_s
+    seconds: (bytes, seconds, hits)."""
+    import oracle
+    probe = min(len(text_np), 1 << 24)
+    t0 = time.perf_counter()
+    oracle.search(text_np[:probe], patterns, threads=threads)
+    rate = probe / max(time.perf_counter() - t0, 1e-3)
+    sample = int(min(len(text_np), max(probe, rate * target_s)))
+    t0 = time.perf_counter()
+    off, _ = oracle.search(text_np[:sample], patterns, threads=threads)
+    return sample, time.perf_counter() - t0, int(off[-1])
+
+
+def cpu_baseline(text_np, pattern: bytes, target_s: float = 8.0):
+    """The oracle as it stands, timed on the host's cores on the first bytes of
+    the same text: one thread, and every usable core (threaded oracle: text
+    chunks with an (m-1)-byte overlap), each sized for about target_s seconds."""
+    h = host_cpu()
+    b1, t1, _ = oracle_rate(text_np, [pattern], 1, target_s)
+    bn, tn, hits = oracle_rate(text_np, [pattern], h["threads"], target_s)
+    return {"value": round(bn / tn / 1e9, 4), "unit": "GB/s", "cores": h["threads"], "kind": "oracle",
+            "sample": "first %d bytes of the same text on %d threads (%.1f s, %d hits); first %d bytes on 1 thread "
+                      "(%.1f s)" % (bn, h["threads"], tn, hits, b1, t1),
+            "value_1core": round(b1 / t1 / 1e9, 4), **h}
 
 
 def run_mode(rk, ctx, text, patterns, mode, steps, warmup):
@@ -194,7 +222,8 @@ def bench_config1(args):
     # result is also the reference the GPU result is checked against
     cpu = {}
     ref = None
-    for threads in (1, min(os.cpu_count() or 1, 16)):
+    hc = host_cpu()
+    for threads in (1, hc["threads"]):
         ts = []
         for _ in range(5):
             t0 = time.perf_counter()
@@ -232,7 +261,8 @@ def bench_config1(args):
         "dtype": "u8", "data": "synthetic",
         "config": {"workload": "single short pattern: %d B i.i.d. a..z text, m=8, 100 planted" % n,
                    "results": out},
-        "cpu_baseline": {"unit": "ms", "kind": "oracle", "sample": "the whole workload", **cpu},
+        "cpu_baseline": {"unit": "ms", "kind": "oracle", "sample": "the whole workload", "cores": hc["threads"],
+                         **cpu, **hc},
     }
     print(json.dumps(line), flush=True)
 
@@ -265,12 +295,15 @@ def bench_config3(args):
     # cpu_baseline leg: the oracle timed on the first 64 MiB; its result also
     # checks the GPU result there (windows wholly inside the prefix)
     pre = 64 << 20
-    threads = min(os.cpu_count() or 1, 16)
+    hc = host_cpu()
+    threads = hc["threads"]
     t0 = time.perf_counter()
     ro, rp = oracle.search(s.text[:pre], s.patterns, threads=threads)
     dt = time.perf_counter() - t0
+    b1, t1, _ = oracle_rate(s.text, s.patterns, 1, 6.0)
     cpu = {"value": round(pre / dt / 1e9, 4), "unit": "GB/s", "cores": threads, "kind": "oracle",
-           "sample": "first 64 MiB of the same text (%.1f s)" % dt}
+           "sample": "first 64 MiB of the same text on %d threads (%.1f s); first %d bytes on 1 thread (%.1f s)"
+                     % (threads, dt, b1, t1), "value_1core": round(b1 / t1 / 1e9, 4), **hc}
     go = first["offsets"].cpu().numpy().astype(np.int64)
     gp = first["positions"].cpu().numpy().astype(np.int64)
     ok = True
@@ -319,7 +352,8 @@ def bench_config4(args):
     # cpu_baseline leg: the oracle timed on a sample of the instances (every
     # len/12-th); its results also check the batched results of both modes
     sample = list(range(0, len(insts), max(1, len(insts) // 12)))
-    threads = min(os.cpu_count() or 1, 16)
+    hc = host_cpu()
+    threads = hc["threads"]
     t0 = time.perf_counter()
     refs = {}
     for i in sample:
@@ -328,7 +362,8 @@ def bench_config4(args):
     dt = time.perf_counter() - t0
     sample_bytes = sum(len(insts[i].text) for i in sample)
     cpu = {"value": round(sample_bytes / dt / 1e9, 4), "unit": "GB/s", "cores": threads, "kind": "oracle",
-           "sample": "%d of the %d instances, %d bytes (%.1f s)" % (len(sample), len(insts), sample_bytes, dt)}
+           "sample": "%d of the %d instances, %d bytes, threaded oracle per instance (%.1f s)"
+                     % (len(sample), len(insts), sample_bytes, dt), **hc}
     res = {}
     for mode in ("screen", "exact") if not args.no_exact else ("screen",):
         bp = rk.BatchPlan(ctx, texts, [s.patterns for s in insts], mode)
@@ -541,6 +576,97 @@ def bench_config5(args):
     print(json.dumps(line), flush=True)
 
 
+# ---------------------------------------------------------------- paper mode
+PAPER_TABLE12_MS = {  # Tables 1-2 (320 MB DNA, m = 7): GT 920 and GT 630M milliseconds per threads/block
+    32: (4718.75, 10638.17), 64: (2708.375, 5931.667), 128: (1715.79, 3600.603), 256: (1220.096, 2434.065),
+    512: (971.2466, 1787.352), 1024: (847.1143, 1495.54)}
+PAPER_TABLE3_MS = {25: 7.51616, 50: 13.82605, 100: 26.37414, 200: 51.32698, 800: 201.1771}  # GT 920, file size unstated
+
+
+def bench_paper(args):
+    """The paper's own experiments rerun on MI355X in paper mode (one thread
+    per offset, the shift-add hash recomputed over m bytes from device
+    memory): a 320e6-byte i.i.d. DNA text, m = 7, threads per block 32..1024
+    (Tables 1-2), then m = 25..800 at 1024 threads per block (Table 3) beside
+    the tiled scans.  One JSON line per point; the paper's own times are
+    context (other GPUs, other file)."""
+    import numpy as np
+    import torch
+    import oracle
+    import rkgen
+    import paper_1810_01051_amd as rk
+    from paper_1810_01051_amd import _lib
+    n = args.paper_n
+    g = rkgen.rng(80, 0)
+    text_np = rkgen.iid_text(g, n, rkgen.ACGT)
+    text = torch.from_numpy(text_np).to("cuda:0")
+    ctx = make_ctx(rk, args)
+    hc = host_cpu()
+
+    def paper_time(pat, tpb, reps):
+        flags = ctx.paper_search(text, pat, tpb)
+        torch.cuda.synchronize()
+        ctx.set_option(_lib.RK_OPT_PROFILE, 1)
+        ctx.profile_reset()
+        for _ in range(reps):
+            ctx.paper_search(text, pat, tpb)
+        k, ms = ctx.profile(5)
+        ctx.set_option(_lib.RK_OPT_PROFILE, 0)
+        ctx.profile_reset()
+        return ms / k, flags
+
+    def tiled_time(pat, mode, reps):
+        return run_mode(rk, ctx, text, [pat], mode, reps, 2)
+
+    def emit(value_ms, extra, cpu=None):
+        line = {"metric": "paper-mode search time (the paper's Tables 1-3)", "value": round(value_ms, 4), "unit": "ms",
+                "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": round(value_ms, 4),
+                "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
+                "data": "synthetic", "config": extra}
+        if cpu:
+            line["cpu_baseline"] = cpu
+        print(json.dumps(line), flush=True)
+
+    # Tables 1-2: m = 7, threads per block 32..1024
+    o = int(g.integers(0, n - 7))
+    pat7 = text_np[o:o + 7].tobytes()
+    ro, rp = oracle.search(text_np, [pat7], threads=hc["threads"])
+    # the paper's sequential loop (the oracle's recompute search, one thread) on a bounded prefix
+    pre = min(n, 32 << 20)
+    t0 = time.perf_counter()
+    oracle.search_recompute(text_np[:pre], [pat7], d=2, q=1 << 32)
+    dt = time.perf_counter() - t0
+    cpu = {"value": round(dt * n / pre * 1e3, 1), "unit": "ms", "cores": 1, "kind": "oracle",
+           "sample": "the paper's sequential loop (hash recomputed per window, d=2, q=2^32) on the first %d bytes "
+                     "in %.2f s, scaled to the whole text" % (pre, dt), **hc}
+    for tpb in (32, 64, 128, 256, 512, 1024):
+        ms, flags = paper_time(pat7, tpb, args.steps)
+        pos = ctx.paper_positions(flags).cpu().numpy().astype(np.uint64)
+        ok = pos.tolist() == rp.tolist()
+        pt = PAPER_TABLE12_MS[tpb]
+        emit(ms, {"workload": "paper mode: %d B i.i.d. ACGT text, m=7, %d threads/block" % (n, tpb),
+                  "threads_per_block": tpb, "m": 7, "GB/s": round(n / (ms / 1e3) / 1e9, 2), "hits": int(pos.size),
+                  "oracle_ok": ok, "paper_ms_GT920": pt[0], "paper_ms_GT630M": pt[1],
+                  "speedup_vs_GT920": round(pt[0] / ms, 1)}, cpu if tpb == 1024 else None)
+        log("paper tpb %d: %.3f ms, oracle %s" % (tpb, ms, ok))
+    # Table 3: pattern length, paper mode at 1024 threads/block beside the tiled scans
+    for m in (25, 50, 100, 200, 800):
+        o = int(g.integers(0, n - m))
+        pat = text_np[o:o + m].tobytes()
+        ms, flags = paper_time(pat, 1024, max(3, args.steps // 2))
+        pos = ctx.paper_positions(flags)
+        tiled = {}
+        for mode in ("screen", "exact"):
+            r = tiled_time(pat, mode, max(3, args.steps // 2))
+            same = bool(torch.equal(r["positions"], pos))
+            tiled[mode] = {"ms_per_step": round(r["ms_per_step"], 4), "scan_ms": round(r["scan_ms"], 4),
+                           "GB/s": round(n / (r["ms_per_step"] / 1e3) / 1e9, 1), "same_positions": same}
+        emit(ms, {"workload": "paper mode: %d B i.i.d. ACGT text, m=%d, 1024 threads/block" % (n, m),
+                  "threads_per_block": 1024, "m": m, "GB/s": round(n / (ms / 1e3) / 1e9, 2),
+                  "hits": int(pos.numel()), "paper_ms_GT920_table3": PAPER_TABLE3_MS[m], "tiled_scan": tiled})
+        log("paper m %d: %.3f ms, tiled %s" % (m, ms, tiled))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -553,9 +679,12 @@ def main():
     ap.add_argument("--tune", default=os.path.join(ROOT, "paper_1810_01051_amd", "autotune_gfx950.json"))
     ap.add_argument("--cfg", type=int, default=-1, help="force a scan geometry (rk_tile_cfg index)")
     ap.add_argument("--grid", type=int, default=0, help="force the persistent grid size")
-    ap.add_argument("--workload", default="config2", choices=["config1", "config2", "config3", "config4", "config5"],
+    ap.add_argument("--workload", default="config2",
+                    choices=["config1", "config2", "config3", "config4", "config5", "paper"],
                     help="config2 (default): the single-pattern DNA scan; config1: the 1 MiB latency case; config3: "
-                         "1,024 patterns over Zipf text; config4: batched uneven instances; config5: serving")
+                         "1,024 patterns over Zipf text; config4: batched uneven instances; config5: serving; "
+                         "paper: the paper's Tables 1-3 in paper mode")
+    ap.add_argument("--paper-n", type=int, default=320 * 10 ** 6, help="paper workload text bytes")
     ap.add_argument("--count4", type=int, default=4096, help="config4 instances")
     ap.add_argument("--corpora", type=int, default=64, help="config5 corpora")
     ap.add_argument("--corpus-bytes", type=int, default=1 << 30, help="config5 bytes per corpus")
@@ -598,6 +727,8 @@ def main():
         return bench_config4(args)
     if args.workload == "config5":
         return bench_config5(args)
+    if args.workload == "paper":
+        return bench_paper(args)
 
     import rkgen
     import paper_1810_01051_amd as rk

@@ -44,7 +44,9 @@
 extern "C" {
 #endif
 
-#define RK_MAX_M 64u                 /* longest pattern the scan kernels accept */
+#define RK_MAX_M 1024u               /* longest pattern (windows longer than RK_STREAM_M are tested by
+                                        their last RK_STREAM_M bytes, then byte-checked whole) */
+#define RK_STREAM_M 64u              /* longest window a scan hashes by rolling */
 #define RK_MAX_PID ((1u << 24) - 1)  /* largest pattern id in one plan (k <= 2^24) */
 #define RK_MAX_N ((1ull << 40) - 1)  /* largest text length (positions are 40-bit) */
 
@@ -56,7 +58,8 @@ typedef enum {
   RK_EDEVICE = -4,      /* HIP runtime error or device fault */
   RK_ENOSPACE = -5,     /* a caller buffer (scratch, work, output capacity) is too small */
   RK_EBUSY = -6,        /* request not finished yet (server poll) */
-  RK_ECANCELED = -7     /* request canceled or its server shut down */
+  RK_ECANCELED = -7,    /* request canceled or its server shut down */
+  RK_ETIMEDOUT = -8     /* request waited longer than the server's request timeout */
 } rk_status;
 
 /* Scan modes.  Both give identical results.
@@ -114,8 +117,8 @@ rk_status rk_tile_cfg(int i, uint32_t *wg, uint32_t *windows_per_thread, uint32_
 
 /* Accumulated device time of scan launches since profiling was switched on.
  * kernel: 0 = scan (count pass), 1 = rescan of overflowed tiles, 2 = collect
- * (compaction + sort), 3 = all, 4 = rk_stream_read.  Synchronises the
- * context's device. */
+ * (compaction + sort), 3 = all of 0..2, 4 = rk_stream_read, 5 = rk_paper_search.
+ * Synchronises the context's device. */
 rk_status rk_ctx_profile(rk_ctx *ctx, int kernel, uint64_t *launches, double *total_ms);
 rk_status rk_ctx_profile_reset(rk_ctx *ctx);
 
@@ -140,12 +143,17 @@ uint32_t rk_plan_patterns(const rk_plan *plan);
  * bytes (a function of n, the plan and RK_OPT_SLAB_CAP). */
 rk_status rk_scratch_size(rk_ctx *ctx, const rk_plan *plan, uint64_t n, uint64_t *bytes);
 
-/* Count pass: scans text_dev[0..n) once, stages hits in scratch_dev and writes
- * the number of hits over all patterns to *total_host.  Synchronises s.
- * scratch must hold rk_scratch_size bytes (RK_ENOSPACE otherwise) and must be
- * passed unchanged to the rk_collect that follows. */
+/* Count pass (the first half of Sec. 1's problem, "find all occurrences":
+ * every window of Sec. 3.1's GPU procedure hashed, tested against the set and
+ * byte-checked): scans text_dev[0..n) once, stages hits in scratch_dev and
+ * writes the number of hits over all patterns to *total_host.  counts_dev
+ * (optional, NULL to skip): k entries (u64, device), pattern j's number of
+ * occurrences.  Synchronises s.  scratch must hold rk_scratch_size bytes
+ * (RK_ENOSPACE otherwise) and must be passed unchanged to the rk_collect that
+ * follows. */
 rk_status rk_count(rk_ctx *ctx, const rk_plan *plan, const uint8_t *text_dev, uint64_t n,
-                   void *scratch_dev, uint64_t scratch_bytes, uint64_t *total_host, rk_stream s);
+                   void *scratch_dev, uint64_t scratch_bytes, uint64_t *counts_dev, uint64_t *total_host,
+                   rk_stream s);
 
 /* Bytes of device work memory rk_collect needs when the count was `total`
  * (0 for single-pattern plans). */
@@ -166,12 +174,20 @@ rk_status rk_collect(rk_ctx *ctx, const rk_plan *plan, const uint8_t *text_dev, 
 rk_status rk_window_hashes(rk_ctx *ctx, const uint8_t *text_dev, uint64_t n, uint32_t m,
                            const uint64_t *xs_dev, uint64_t cnt, uint64_t *out_dev, rk_stream s);
 
-/* Hash dump of the scan itself: runs the exact-mode scan kernel for length m
- * over text_dev[0..n) and writes, from its rolling state, the hash of window
- * x = i * stride to out_dev[i] for i < cnt = floor((n - m) / stride) + 1.
- * cap = entries of out_dev (RK_ENOSPACE if below cnt). */
+/* Hash dump of the scan itself (the "identical window hashes on sampled
+ * dumps" check of the exact path): runs an exact-mode scan kernel for length m
+ * over text_dev[0..n) and writes, from the rolling state of its own hash loop
+ * (the same initial state, rolling step and out-stream as its pattern test),
+ * the canonical hash of window x = i * stride to out_dev[i] for
+ * i < cnt = floor((n - m) / stride) + 1, for 1 <= m <= RK_STREAM_M
+ * (RK_EUNSUPPORTED above: longer patterns are tested by the hash of their
+ * last RK_STREAM_M bytes).  kernel 0: the general scan kernel
+ * (pattern sets, batches); 1: the single-bucket kernel that one-pattern
+ * searches run.  The geometry is RK_OPT_TILE_CFG's, else the autotuned one
+ * for (exact, m).  cap = entries of out_dev (RK_ENOSPACE if below cnt).
+ * Synchronises s.  (Sec. 3.1: the window hash of every offset.) */
 rk_status rk_scan_dump(rk_ctx *ctx, const uint8_t *text_dev, uint64_t n, uint32_t m,
-                       uint64_t stride, uint64_t *out_dev, uint64_t cap, rk_stream s);
+                       uint64_t stride, uint64_t *out_dev, uint64_t cap, int kernel, rk_stream s);
 
 /* Read-bandwidth ceiling for the scan's roofline: reads data_dev[0..n) once
  * with coalesced 16-byte loads (grid workgroups of 256 threads, grid-stride)
@@ -179,6 +195,62 @@ rk_status rk_scan_dump(rk_ctx *ctx, const uint8_t *text_dev, uint64_t n, uint32_
  * 16-byte aligned, n a multiple of 16.  Timed by RK_OPT_PROFILE as kernel 4. */
 rk_status rk_stream_read(rk_ctx *ctx, const void *data_dev, uint64_t n, uint32_t *out_dev, uint32_t grid,
                          rk_stream s);
+
+/* ------------------------------------------- texts in host memory or a file */
+
+/* Result of a streamed search, in host memory owned by the library: pattern
+ * j's ascending positions are positions[offsets[j] .. offsets[j+1]). */
+typedef struct {
+  uint32_t k;
+  uint64_t total;
+  uint64_t *offsets;    /* k + 1 entries */
+  uint64_t *positions;  /* total entries */
+} rk_host_result;
+
+/* Search of a text that lives in host memory (text_host, n bytes, any
+ * alignment, pageable) -- of any length, device memory holding only two
+ * pieces of piece_bytes (rounded up to 16; at least 64 KiB and twice the
+ * longest pattern).  The paper reads T and P from files and moves them to the
+ * device (Sec. 3.1); here the text moves piece by piece: piece i owns the
+ * windows starting in [i L, (i+1) L), L = piece_bytes - (m_max - 1), and holds
+ * the m_max - 1 bytes after them, so each window is searched in exactly one
+ * piece.  Staging of the next piece (host threads), its host-to-device copy
+ * and the search of the current one overlap.  plan: a single-text plan (not a
+ * batch).  *out receives the result (free with rk_host_result_free).
+ * Allocates device memory for the pieces, scratch and each piece's hits. */
+rk_status rk_search_host(rk_ctx *ctx, const rk_plan *plan, const uint8_t *text_host, uint64_t n,
+                         uint64_t piece_bytes, rk_host_result **out);
+/* The same for the bytes of the file at path (read with pread, piece by piece). */
+rk_status rk_search_file(rk_ctx *ctx, const rk_plan *plan, const char *path, uint64_t piece_bytes,
+                         rk_host_result **out);
+void rk_host_result_free(rk_host_result *r);
+
+/* ------------------------------------------------------- paper-faithful mode */
+
+/* The paper's GPU procedure as printed (Sec. 3.1), for rerunning its
+ * experiments (Tables 1-3: threads per block, pattern length) next to the
+ * tiled scans: one thread per offset x in [0, n - m] (grid of
+ * ceil((n - m + 1) / threads_per_block) blocks of threads_per_block threads,
+ * 1..1024), each hashing the m bytes at text_dev + x with h <- (h << 1) + c in
+ * a 32-bit word (d = 2, q = 2^32) read straight from device memory, comparing
+ * with the pattern's hash (computed here on the host from pattern_host) and,
+ * on equality, comparing the m bytes with pattern_dev.  result_dev[x] = 1 for
+ * a match, 0 otherwise (n - m + 1 bytes, the paper's result array).  hash_dev
+ * (optional, NULL to skip): n - m + 1 u32, every window's hash.  Any m >= 1;
+ * m > n launches nothing.  text_dev needs no alignment.  Asynchronous on s;
+ * timed by RK_OPT_PROFILE as kernel 5. */
+rk_status rk_paper_search(rk_ctx *ctx, const uint8_t *text_dev, uint64_t n, const uint8_t *pattern_dev,
+                          const uint8_t *pattern_host, uint32_t m, uint32_t threads_per_block,
+                          uint8_t *result_dev, uint32_t *hash_dev, rk_stream s);
+/* Device scratch bytes rk_paper_positions needs for nflags result bytes. */
+rk_status rk_paper_scratch_size(uint64_t nflags, uint64_t *bytes);
+/* Ascending positions of the nonzero bytes of flags_dev[0..nflags) (a result
+ * array of rk_paper_search) into positions_dev (capacity entries; RK_ENOSPACE
+ * if fewer than the count, which *total_host still receives).  Synchronises s
+ * once (for the count). */
+rk_status rk_paper_positions(rk_ctx *ctx, const uint8_t *flags_dev, uint64_t nflags, void *scratch_dev,
+                             uint64_t scratch_bytes, uint64_t *positions_dev, uint64_t capacity,
+                             uint64_t *total_host, rk_stream s);
 
 /* ----------------------------------------------------------------- batching */
 

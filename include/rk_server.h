@@ -18,8 +18,13 @@
  * host gets per-pattern offsets, and positions on demand).
  * Several steps are in flight at once on separate streams, so requests that
  * arrive while others run on the device are admitted as slots and arena space
- * free up.  Launches of a step are replayed from HIP graphs captured once per
- * stream slot, with the kernel parameters of each step set on the graph.
+ * free up.  With use_graphs, the count and the collect pass of a step are each
+ * captured into a graph that updates the slot's executable graph in place
+ * (re-instantiated only when the launch sequence changes) and launched as one
+ * unit.  A step that fails for lack of memory before it reaches the device
+ * (host or device allocations of its plan) goes back to the queue and later
+ * steps take fewer requests; a single request that fails that way, and every
+ * step that fails on the device, end with the error.
  *
  * Results are exact and identical to a solo rk_count/rk_collect of the same
  * request: merging only changes which patterns share a scan.
@@ -41,9 +46,10 @@ typedef struct {
                                   until the arena can hold it, so results must be released
                                   as they are consumed.  Requests complete out of submission
                                   order (a later request for the oldest request's corpus joins
-                                  its step), so a client that releases only in submission
-                                  order, or waits for every request before releasing any, can
-                                  stall the arena. */
+                                  its step): a client that releases only in submission order,
+                                  or waits for every request before releasing any, can hold
+                                  the arena full; such a step ends RK_ENOSPACE after
+                                  admission_timeout_s. */
   uint32_t max_inflight;       /* steps in flight on the device, 1..8 (default 2) */
   uint32_t max_step_requests;  /* requests merged into one step (default 4096) */
   uint32_t max_step_patterns;  /* merged patterns per step (default 1024; a request with
@@ -54,14 +60,22 @@ typedef struct {
                                   steps of 256 / 512 / 1,024 / 2,048 / 262,144 merged
                                   patterns served 458 / 663 / 808 / 563 / 305 req/s. */
   int mode;                    /* rk_mode of every search */
-  int use_graphs;              /* 1: replay captured HIP graphs; 0: plain launches */
+  int use_graphs;              /* 1: launch each step's passes as HIP graphs (captured per step into the
+                                  slot's executable graph, updated in place); 0: plain launches */
+  double admission_timeout_s;  /* a counted step that finds no arena space while no other step is in
+                                  flight (only unreleased results hold the arena) waits at most this
+                                  long for the client to release some, then its requests end
+                                  RK_ENOSPACE (default 2 s; a step never waits forever) */
+  double request_timeout_s;    /* a request still waiting for a step after this long ends
+                                  RK_ETIMEDOUT (0, the default: no limit) */
 } rk_server_cfg;
 
 /* Fills cfg with the defaults above. */
 void rk_server_cfg_default(rk_server_cfg *cfg);
 
 typedef struct {
-  rk_status status;            /* RK_OK done, RK_EBUSY pending, RK_ECANCELED, or the step's error */
+  rk_status status;            /* RK_OK done, RK_EBUSY pending, RK_ECANCELED, RK_ETIMEDOUT, RK_ENOSPACE
+                                  (admission timed out), or the step's error */
   uint32_t k;                  /* patterns of the request */
   const uint64_t *offsets;     /* host, k+1 entries; valid until rk_server_release */
   const uint64_t *positions_dev; /* device (server arena), offsets[k] entries, per pattern

@@ -15,7 +15,7 @@
  *     base d and the modulus q as parameters, defaulting to d = 256,
  *     q = 2^61 - 1);
  *   - a window x is reported for pattern P iff hy(x) == hx and the bytes
- *     compare equal (the paper's "compare hash and match pattern" step);
+ *     compare equal (Sec. 3.1: bytes are compared only after the hashes agree);
  *   - windows run over every x in [0, n-m] inclusive (the GPU pseudo code's
  *     guard x <= n-m; the sequential loop bound x < n-m would drop the last
  *     window, which is read as a slip);

@@ -20,8 +20,9 @@ RK_EDEVICE = -4
 RK_ENOSPACE = -5
 RK_EBUSY = -6
 RK_ECANCELED = -7
+RK_ETIMEDOUT = -8
 STATUS_NAMES = {0: "RK_OK", -1: "RK_EINVAL", -2: "RK_ENOMEM", -3: "RK_EUNSUPPORTED", -4: "RK_EDEVICE",
-                -5: "RK_ENOSPACE", -6: "RK_EBUSY", -7: "RK_ECANCELED"}
+                -5: "RK_ENOSPACE", -6: "RK_EBUSY", -7: "RK_ECANCELED", -8: "RK_ETIMEDOUT"}
 
 RK_MODE_AUTO = 0
 RK_MODE_EXACT = 1
@@ -33,7 +34,8 @@ RK_OPT_GRID = 3
 RK_OPT_PROFILE = 4
 RK_OPT_QUEUE = 5
 
-RK_MAX_M = 64
+RK_MAX_M = 1024
+RK_STREAM_M = 64
 
 c_u8p = ctypes.POINTER(ctypes.c_uint8)
 c_u64p = ctypes.POINTER(ctypes.c_uint64)
@@ -46,10 +48,15 @@ class RkInstance(ctypes.Structure):
                 ("offsets_host", c_void), ("k", ctypes.c_uint32)]
 
 
+class RkHostResult(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_uint32), ("total", ctypes.c_uint64), ("offsets", c_u64p), ("positions", c_u64p)]
+
+
 class RkServerCfg(ctypes.Structure):
     _fields_ = [("arena_bytes", ctypes.c_uint64), ("max_inflight", ctypes.c_uint32),
                 ("max_step_requests", ctypes.c_uint32), ("max_step_patterns", ctypes.c_uint32),
-                ("mode", ctypes.c_int), ("use_graphs", ctypes.c_int)]
+                ("mode", ctypes.c_int), ("use_graphs", ctypes.c_int), ("admission_timeout_s", ctypes.c_double),
+                ("request_timeout_s", ctypes.c_double)]
 
 
 class RkResultView(ctypes.Structure):
@@ -99,7 +106,7 @@ SIGNATURES = {
     "rk_plan_destroy": (None, [c_void]),
     "rk_plan_patterns": (ctypes.c_uint32, [c_void]),
     "rk_scratch_size": (ctypes.c_int, [c_void, c_void, ctypes.c_uint64, c_u64p]),
-    "rk_count": (ctypes.c_int, [c_void, c_void, c_void, ctypes.c_uint64, c_void, ctypes.c_uint64, c_u64p,
+    "rk_count": (ctypes.c_int, [c_void, c_void, c_void, ctypes.c_uint64, c_void, ctypes.c_uint64, c_void, c_u64p,
                                 c_void]),
     "rk_work_size": (ctypes.c_int, [c_void, c_void, ctypes.c_uint64, c_u64p]),
     "rk_collect": (ctypes.c_int, [c_void, c_void, c_void, ctypes.c_uint64, c_void, ctypes.c_uint64, c_void,
@@ -107,10 +114,20 @@ SIGNATURES = {
     "rk_window_hashes": (ctypes.c_int, [c_void, c_void, ctypes.c_uint64, ctypes.c_uint32, c_void,
                                         ctypes.c_uint64, c_void, c_void]),
     "rk_scan_dump": (ctypes.c_int, [c_void, c_void, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64, c_void,
-                                    ctypes.c_uint64, c_void]),
+                                    ctypes.c_uint64, ctypes.c_int, c_void]),
     "rk_batch_plan_create": (ctypes.c_int, [c_void, ctypes.POINTER(RkInstance), ctypes.c_uint32, ctypes.c_int,
                                             ctypes.POINTER(c_void)]),
     "rk_plan_text_bytes": (ctypes.c_uint64, [c_void]),
+    "rk_search_host": (ctypes.c_int, [c_void, c_void, c_void, ctypes.c_uint64, ctypes.c_uint64,
+                                      ctypes.POINTER(ctypes.POINTER(RkHostResult))]),
+    "rk_search_file": (ctypes.c_int, [c_void, c_void, ctypes.c_char_p, ctypes.c_uint64,
+                                      ctypes.POINTER(ctypes.POINTER(RkHostResult))]),
+    "rk_host_result_free": (None, [ctypes.POINTER(RkHostResult)]),
+    "rk_paper_search": (ctypes.c_int, [c_void, c_void, ctypes.c_uint64, c_void, c_void, ctypes.c_uint32,
+                                       ctypes.c_uint32, c_void, c_void, c_void]),
+    "rk_paper_scratch_size": (ctypes.c_int, [ctypes.c_uint64, c_u64p]),
+    "rk_paper_positions": (ctypes.c_int, [c_void, c_void, ctypes.c_uint64, c_void, ctypes.c_uint64, c_void,
+                                          ctypes.c_uint64, c_u64p, c_void]),
     "rk_stream_read": (ctypes.c_int, [c_void, c_void, ctypes.c_uint64, c_void, ctypes.c_uint32, c_void]),
     "rk_autotune": (ctypes.c_int, [c_void, ctypes.c_uint64, c_u32p, ctypes.c_uint32, ctypes.c_char_p]),
     "rk_autotune_load": (ctypes.c_int, [c_void, ctypes.c_char_p]),

@@ -17,9 +17,9 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librk.so")
-SOURCES = ["rk_scan_exact_256x132.hip", "rk_scan_exact_512x68.hip", "rk_scan_exact_256x68.hip", "rk_scan_exact_256x36.hip",
-           "rk_scan_screen.hip", "rk_device.hip", "rk_host.cpp",
-           "rk_exec.cpp", "rk_tune.cpp", "rk_server.cpp"]
+SOURCES = (["rk_%s_exact_%s.hip" % (k, g) for g in ("256x132", "512x68", "256x68", "256x36") for k in ("scan", "list")] +
+           ["rk_scan_screen.hip", "rk_device.hip", "rk_paper.hip", "rk_host.cpp", "rk_exec.cpp", "rk_tune.cpp",
+            "rk_stream.cpp", "rk_server.cpp"])
 ARCH = os.environ.get("RK_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", "-Wno-unused-value", "-Wno-unused-result",
          # packed fp32 instructions are kept out of every kernel

@@ -357,12 +357,16 @@ hipError_t list_scan(int cfg, int fam, const ListParams *p, uint32_t grid, hipSt
 }
 
 static hipError_t prepare_scan_kernel(int fam, int cfg) { RK_SCAN_DISPATCH(fam, cfg, prepare()) }
+static hipError_t prepare_list_kernel(int fam, int cfg) { RK_SCAN_DISPATCH(fam, cfg, list_prepare()) }
 
 // Raises the dynamic LDS limit of every scan kernel once, outside any stream
 // capture (a graph capture must not run first-time setup calls).
 void prepare_scan_kernels() {
   for (int fam : {kFamScreen1, kFamScreen, kFamExact})
-    for (int cfg = 0; cfg < kNumTileCfg; ++cfg) (void)prepare_scan_kernel(fam, cfg);
+    for (int cfg = 0; cfg < kNumTileCfg; ++cfg) {
+      (void)prepare_scan_kernel(fam, cfg);
+      (void)prepare_list_kernel(fam, cfg);
+    }
 }
 
 // ----------------------------------------------------- stream-read roofline

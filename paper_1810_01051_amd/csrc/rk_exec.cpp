@@ -64,6 +64,7 @@ rk_status plan_build_host(rk_ctx *ctx, const rk_instance *inst, uint32_t count, 
     for (uint32_t j = 0; j < I.k; ++j) {
       const uint32_t m = (uint32_t)(I.offsets_host[j + 1] - I.offsets_host[j]);
       mweight[m] += (double)(batch ? I.n : 1) + 1.0;
+      P->max_m = std::max(P->max_m, m);
     }
     ktot += I.k;
     P->text_bytes += batch ? I.n : 0;
@@ -247,7 +248,7 @@ static uint32_t pid_bits(uint32_t k) {
   return b;
 }
 
-static hipError_t prof_begin(rk_ctx *ctx, hipStream_t s, int kind, int *slot) {
+hipError_t prof_begin(rk_ctx *ctx, hipStream_t s, int kind, int *slot) {
   *slot = -1;
   if (!ctx->profile) return hipSuccess;
   ProfEvent ev;
@@ -266,7 +267,7 @@ static hipError_t prof_begin(rk_ctx *ctx, hipStream_t s, int kind, int *slot) {
   return hipEventRecord(ev.a, s);
 }
 
-static hipError_t prof_end(rk_ctx *ctx, hipStream_t s, int slot) {
+hipError_t prof_end(rk_ctx *ctx, hipStream_t s, int slot) {
   if (slot < 0) return hipSuccess;
   return hipEventRecord(ctx->prof_events[slot].b, s);
 }
@@ -300,7 +301,7 @@ static void base_params(const rk_plan *plan, const Layout &L, uint8_t *sc, ScanP
 }
 
 rk_status count_enqueue(rk_ctx *ctx, const rk_plan *plan, const uint8_t *text, uint64_t n, void *scratch,
-                        uint64_t scratch_bytes, hipStream_t s) {
+                        uint64_t scratch_bytes, uint64_t *counts, hipStream_t s) {
   if (plan->device != ctx->device) return set_err(ctx, RK_EINVAL, "plan belongs to another device");
   if (plan->batch) {
     if (text) return set_err(ctx, RK_EINVAL, "batch plans take text_dev = NULL");
@@ -336,12 +337,17 @@ rk_status count_enqueue(rk_ctx *ctx, const rk_plan *plan, const uint8_t *text, u
   }
   e = launch_fill_u32((uint32_t *)(sc + L.ctr), 64, 0u, s);
   if (e != hipSuccess) return hip_err(ctx, e, "counter reset");
+  if (counts) {
+    e = launch_fill_u32((uint32_t *)counts, 2ull * plan->k_total, 0u, s);
+    if (e != hipSuccess) return hip_err(ctx, e, "per-pattern count reset");
+  }
   if (L.T == 0) return RK_OK;
   ScanParams p;
   base_params(plan, L, sc, p);
   p.items = plan->batch ? plan->items_dev : nullptr;
   p.nitems = plan->batch ? plan->nitems : L.T;
   p.out = (uint64_t *)(sc + L.slabs);
+  p.pid_counts = (unsigned long long *)counts;
   const bool use_queue = ctx->queue == 1 || (ctx->queue == -1 && plan->batch);
   if (use_queue) {
     p.queue = (uint32_t *)(sc + L.ctr + 12);
@@ -366,6 +372,7 @@ rk_status count_enqueue(rk_ctx *ctx, const rk_plan *plan, const uint8_t *text, u
     lp.total = p.total;
     lp.ovf_count = p.ovf_count;
     lp.ovf_list = p.ovf_list;
+    lp.pid_counts = p.pid_counts;
     uint32_t grid = ctx->grid;
     if (!grid) {
       int blocks = 0;
@@ -529,11 +536,14 @@ rk_status collect_enqueue_known(rk_ctx *ctx, const rk_plan *plan, uint64_t n, vo
 using namespace rk;
 
 extern "C" rk_status rk_scan_dump(rk_ctx *ctx, const uint8_t *text, uint64_t n, uint32_t m, uint64_t stride,
-                                  uint64_t *out, uint64_t cap, rk_stream s) {
+                                  uint64_t *out, uint64_t cap, int kernel, rk_stream s) {
   if (!ctx) return RK_EINVAL;
   if (m == 0) return set_err(ctx, RK_EINVAL, "m = 0");
-  if (m > RK_MAX_M) return set_err(ctx, RK_EUNSUPPORTED, "m > %u", RK_MAX_M);
+  if (m > kStreamM)
+    return set_err(ctx, RK_EUNSUPPORTED, "m > %u: the scans roll windows of up to %u bytes (rk_window_hashes "
+                   "evaluates any length)", kStreamM, kStreamM);
   if (stride == 0) return set_err(ctx, RK_EINVAL, "stride = 0");
+  if (kernel != 0 && kernel != 1) return set_err(ctx, RK_EINVAL, "kernel is 0 (general) or 1 (single-bucket)");
   if (n < m) return RK_OK;
   if (!text || !out) return set_err(ctx, RK_EINVAL, "null pointer");
   if (((uintptr_t)text & 15u) != 0) return set_err(ctx, RK_EINVAL, "text_dev must be 16-byte aligned");
@@ -542,17 +552,42 @@ extern "C" rk_status rk_scan_dump(rk_ctx *ctx, const uint8_t *text, uint64_t n, 
   if (cap < cnt) return set_err(ctx, RK_ENOSPACE, "dump needs %llu entries", (unsigned long long)cnt);
   if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, RK_EDEVICE, "hipSetDevice failed");
   hipStream_t st = (hipStream_t)s;
-  const int cfg = ctx->tile_cfg >= 0 ? ctx->tile_cfg : 0;
+  const int cfg = pick_cfg(ctx, RK_MODE_EXACT, m);
   const uint32_t W = kTileCfgs[cfg].wg * kTileCfgs[cfg].c;
-  // image: header + one kDump bucket; then the instance descriptor
-  uint8_t host[256];
-  memset(host, 0, sizeof host);
-  ImageHeader hd = {1u, 128u, m, 128u};
+  const uint64_t ntiles = (n + W - 1) / W;
   BucketDesc d;
   memset(&d, 0, sizeof d);
   d.m = m;
   d.kind = kDump;
   d.mask = 0xFFFFFFFFu;
+  hipError_t e;
+  if (kernel == 1) {
+    ListParams lp;
+    memset(&lp, 0, sizeof lp);
+    lp.text = text;
+    lp.n = n;
+    lp.ntiles = ntiles;
+    lp.D = d;
+    lp.rot = (8u * m) % 61u;
+    lp.dump_out = out;
+    lp.dump_stride = stride;
+    lp.dump_cap = cap;
+    uint32_t grid = ctx->grid;
+    if (!grid) {
+      int blocks = 0;
+      if (list_scan(cfg, kFamExact, nullptr, 0, nullptr, &blocks) != hipSuccess || blocks < 1) blocks = 1;
+      grid = (uint32_t)ctx->num_cu * (uint32_t)blocks;
+    }
+    grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(grid, ntiles));
+    e = list_scan(cfg, kFamExact, &lp, grid, st, nullptr);
+    if (e != hipSuccess) return hip_err(ctx, e, "dump launch");
+    e = hipStreamSynchronize(st);
+    return e == hipSuccess ? RK_OK : hip_err(ctx, e, "dump");
+  }
+  // image: header + one kDump bucket; then the instance descriptor
+  uint8_t host[256];
+  memset(host, 0, sizeof host);
+  ImageHeader hd = {1u, 128u, m, 128u};
   memcpy(host, &hd, sizeof hd);
   memcpy(host + sizeof hd, &d, sizeof d);
   InstDesc I;
@@ -560,11 +595,10 @@ extern "C" rk_status rk_scan_dump(rk_ctx *ctx, const uint8_t *text, uint64_t n, 
   I.text = text;
   I.n = n;
   I.tile_base = 0;
-  I.ntiles = (n + W - 1) / W;
+  I.ntiles = ntiles;
   I.img_off = 0;
   I.lds_bytes = 128;
   memcpy(host + 128, &I, sizeof I);
-  hipError_t e;
   if (!ctx->dump_dev) {
     e = hipMalloc(&ctx->dump_dev, 256);
     if (e != hipSuccess) return hip_err(ctx, e, "dump buffer");
@@ -583,7 +617,7 @@ extern "C" rk_status rk_scan_dump(rk_ctx *ctx, const uint8_t *text, uint64_t n, 
   p.dump_stride = stride;
   p.dump_cap = cap;
   const uint32_t lds = scan_lds_bytes(cfg, 128);
-  uint32_t grid = (uint32_t)std::min<uint64_t>(I.ntiles, (uint64_t)ctx->num_cu * 4);
+  const uint32_t grid = scan_grid(ctx, cfg, kFamExact, lds, I.ntiles);
   e = launch_scan(cfg, kFamExact, p, grid, lds, st);
   if (e != hipSuccess) return hip_err(ctx, e, "dump launch");
   e = hipStreamSynchronize(st);

@@ -110,9 +110,12 @@ struct GroupIn {
 
 static uint32_t screen_mask(uint32_t m) { return (screen_shift(m) == 8 && m < 4) ? (1u << (8 * m)) - 1u : 0xFFFFFFFFu; }
 
-// group id for a pattern length under a mode
+// group id for a pattern length under a mode: exact mode has one stream per
+// length up to kStreamM, and every longer pattern joins the kStreamM stream
+// (keyed by the hash of its last kStreamM bytes)
 static uint32_t group_id(int mode, uint32_t m) {
-  if (mode == RK_MODE_EXACT || m < 4) return m;
+  if (mode == RK_MODE_EXACT) return std::min(m, kStreamM);
+  if (m < 4) return m;
   return 100 + screen_shift(m);
 }
 
@@ -259,9 +262,10 @@ static bool emit_group(const GroupIn &G, GroupBody &out) {
       pb.insert(pb.end(), P[i].p, P[i].p + P[i].m);
       pb.resize(align_up(pb.size(), 4), 0);
     }
-    ents[i].off_m = off | (P[i].m << 24);  // offset relative to the pattern block
+    ents[i].off_m = om_pack(off, P[i].m);  // offset relative to the pattern block
     max_m = std::max(max_m, P[i].m);
   }
+  if (pb.size() > kGroupPatBytes) return false;  // split: entries address 4 MiB of pattern bytes
   if (table) {
     // one record per cuckoo slot: the run of entries whose table key sits in
     // that slot, a single entry held inline
@@ -415,14 +419,17 @@ static std::vector<GroupIn> group_patterns(const uint8_t *bytes, const uint64_t 
     r.p = p;
     r.m = m;
     r.hx = host_hash(p, m);
+    // the window a group's stream hashes: the whole pattern, or its last
+    // kStreamM bytes in exact mode
+    const uint32_t ms = mode == RK_MODE_EXACT ? std::min(m, kStreamM) : m;
     if (G.pats.empty()) {
       G.screen = mode != RK_MODE_EXACT;
       G.shift = screen_shift(m);
       G.mask = screen_mask(m);
-      G.m = m;
+      G.m = ms;
     }
-    G.m = std::min(G.m, m);
-    r.key = G.screen ? (uint64_t)screen_hash(p, m) : r.hx;
+    G.m = std::min(G.m, ms);
+    r.key = G.screen ? (uint64_t)screen_hash(p, m) : (m > kStreamM ? host_hash(p + m - kStreamM, kStreamM) : r.hx);
     G.pats.push_back(r);
   }
   std::vector<GroupIn> out;
@@ -456,6 +463,7 @@ const char *rk_status_string(rk_status s) {
     case RK_ENOSPACE: return "RK_ENOSPACE";
     case RK_EBUSY: return "RK_EBUSY";
     case RK_ECANCELED: return "RK_ECANCELED";
+    case RK_ETIMEDOUT: return "RK_ETIMEDOUT";
   }
   return "RK_UNKNOWN";
 }
@@ -589,11 +597,11 @@ rk_status rk_work_size(rk_ctx *ctx, const rk_plan *plan, uint64_t total, uint64_
 }
 
 rk_status rk_count(rk_ctx *ctx, const rk_plan *plan, const uint8_t *text, uint64_t n, void *scratch,
-                   uint64_t scratch_bytes, uint64_t *total_host, rk_stream s) {
+                   uint64_t scratch_bytes, uint64_t *counts_dev, uint64_t *total_host, rk_stream s) {
   if (!ctx || !plan || !total_host) return RK_EINVAL;
   hipStream_t st = (hipStream_t)s;
   uint64_t total = 0;
-  rk_status r = count_enqueue(ctx, plan, text, n, scratch, scratch_bytes, st);
+  rk_status r = count_enqueue(ctx, plan, text, n, scratch, scratch_bytes, counts_dev, st);
   if (r != RK_OK) return r;
   r = count_finish(ctx, plan, scratch, st, &total);
   if (r != RK_OK) return r;

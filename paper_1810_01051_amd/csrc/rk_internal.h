@@ -10,7 +10,9 @@
 namespace rk {
 
 constexpr uint64_t kQ = (1ull << 61) - 1;  // Mersenne modulus 2^61 - 1
-constexpr uint32_t kFront = 64;            // halo bytes kept in front of a tile (>= RK_MAX_M)
+constexpr uint32_t kFront = 64;            // halo bytes kept in front of a tile (= kStreamM)
+constexpr uint32_t kStreamM = 64;          // longest window hashed by a rolling stream; longer patterns are
+                                           // keyed by their last kStreamM bytes
 constexpr uint32_t kPosBits = 40;          // hit record = pid << 40 | start position
 constexpr uint64_t kPosMask = (1ull << kPosBits) - 1;
 constexpr uint32_t kCandCap = 512;         // candidate slots in LDS per workgroup
@@ -52,9 +54,18 @@ static_assert(sizeof(BucketDesc) == 64, "bucket descriptor is 64 bytes");
 struct Entry {
   uint64_t hx;     // exact hash of the pattern, canonical
   uint32_t pid;    // global pattern id
-  uint32_t off_m;  // byte offset of the pattern (bits 0-23) | length << 24
+  uint32_t off_m;  // om_pack(byte offset of the pattern, length)
 };
 static_assert(sizeof(Entry) == 16, "entry is 16 bytes");
+
+// Pattern reference of an entry: byte offset in its group's pattern block
+// (bits 0-21, so a group holds at most 4 MiB of pattern bytes) and length - 1
+// (bits 22-31, lengths 1..1024).
+constexpr uint32_t kOmOffBits = 22;
+constexpr uint32_t kGroupPatBytes = 1u << kOmOffBits;
+__host__ __device__ inline uint32_t om_pack(uint32_t off, uint32_t m) { return off | ((m - 1u) << kOmOffBits); }
+__host__ __device__ inline uint32_t om_len(uint32_t om) { return (om >> kOmOffBits) + 1u; }
+__host__ __device__ inline uint32_t om_off(uint32_t om) { return om & (kGroupPatBytes - 1u); }
 
 // Record of a key (list kinds: in the key table; table kinds: per cuckoo
 // slot): the run of entries with that key, or the single entry inline.
@@ -122,6 +133,7 @@ struct ScanParams {
   uint64_t *dump_out;         // kDump buckets: destination of sampled hashes
   uint64_t dump_stride;
   uint64_t dump_cap;
+  unsigned long long *pid_counts; // count mode, optional: hits per global pattern id
 };
 
 // Kernel parameters of the single-bucket scan (one text, one bucket whose set
@@ -140,6 +152,10 @@ struct ListParams {
   unsigned long long *total;
   uint32_t *ovf_count;
   uint64_t *ovf_list;
+  uint64_t *dump_out;         // kDump bucket: destination of sampled hashes (no counts then)
+  uint64_t dump_stride;
+  uint64_t dump_cap;
+  unsigned long long *pid_counts; // optional: hits per pattern id
 };
 
 // Host-side geometry table (workgroup size, windows per thread).

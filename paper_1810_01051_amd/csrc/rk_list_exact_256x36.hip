@@ -1,0 +1,8 @@
+// Exact family (d = 256, q = 2^61 - 1; hash dump), single-bucket kernel, tile geometry
+// 256x36 (workgroup size x windows per thread): one kernel per translation unit,
+// so that the exact kernels compile in parallel.
+#include "rk_scan.h"
+
+namespace rk {
+RK_INSTANTIATE_LIST(kFamExact, 3)
+}  // namespace rk

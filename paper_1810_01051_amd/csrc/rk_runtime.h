@@ -77,6 +77,7 @@ struct rk_plan {
   rk::BucketDesc list_desc;   // that bucket
   uint64_t list_rec1 = 0;     // its key's record when it has a single key
   uint64_t text_bytes = 0;
+  uint32_t max_m = 0;         // longest pattern
   std::vector<rk::RealInst> insts;
   std::vector<rk::VInst> vinsts;
   void *dev = nullptr;        // one device allocation: blob | instance descs | items
@@ -110,7 +111,7 @@ rk_status plan_build(rk_ctx *ctx, const rk_instance *inst, uint32_t count, int m
 rk_status make_layout(rk_ctx *ctx, const rk_plan *plan, uint64_t n, Layout &L);
 uint64_t work_bytes_for(const rk_plan *plan, uint64_t total);
 rk_status count_enqueue(rk_ctx *ctx, const rk_plan *plan, const uint8_t *text, uint64_t n, void *scratch,
-                        uint64_t scratch_bytes, hipStream_t s);
+                        uint64_t scratch_bytes, uint64_t *counts, hipStream_t s);
 rk_status count_finish(rk_ctx *ctx, const rk_plan *plan, void *scratch, hipStream_t s, uint64_t *total);
 rk_status collect_enqueue(rk_ctx *ctx, const rk_plan *plan, const uint8_t *text, uint64_t n, void *scratch,
                           uint64_t scratch_bytes, void *work, uint64_t work_bytes, uint64_t *offsets,
@@ -123,18 +124,26 @@ rk_status plan_build_host(rk_ctx *ctx, const rk_instance *inst, uint32_t count, 
 void plan_sizes(const std::vector<uint8_t> &blob, const std::vector<InstDesc> &descs, const std::vector<uint64_t> &items,
                 uint64_t *blob_bytes, uint64_t *desc_bytes, uint64_t *item_bytes);
 void prepare_scan_kernels();
+// HIP events around one launch on s when profiling is on (kind: the
+// rk_ctx_profile kernel class); slot -1 when off
+hipError_t prof_begin(rk_ctx *ctx, hipStream_t s, int kind, int *slot);
+hipError_t prof_end(rk_ctx *ctx, hipStream_t s, int slot);
 hipError_t launch_stream_read(const void *data, uint64_t n, uint32_t *out, uint32_t grid, hipStream_t s);
 
 // Launchers of the scan kernels of one family (kFamScreen1 / kFamScreen /
 // kFamExact) and one geometry CFG of kTileCfgs.  The kernels are defined in
-// rk_scan.h and instantiated in the rk_scan_*.hip translation units (split so
-// that they compile in parallel); every other unit sees these declarations only.
+// rk_scan.h and instantiated in the rk_scan_*.hip translation units (split by
+// family, geometry and kernel so that they compile in parallel); every other
+// unit sees these declarations only.
 template <int FAM, int CFG>
 struct ScanGeom {
+  // the general scan kernel
   static hipError_t launch(const ScanParams &p, uint32_t grid, uint32_t lds_bytes, hipStream_t s);
   static hipError_t occupancy(uint32_t lds_bytes, int *blocks);
-  static hipError_t list(const ListParams *p, uint32_t grid, hipStream_t s, int *blocks);
   static hipError_t prepare();
+  // the single-bucket kernel
+  static hipError_t list(const ListParams *p, uint32_t grid, hipStream_t s, int *blocks);
+  static hipError_t list_prepare();
 };
 
 // device translation unit

@@ -470,12 +470,17 @@ __device__ __forceinline__ OutStream out_stream(const uint8_t *mine, uint32_t m)
   return os;
 }
 
-template <int C, bool ANY, bool TABLE, int NT, int OUTK>
-__device__ __forceinline__ void pass_exact_w(const uint32_t *w, const uint32_t *d, OutStream os, uint32_t m, uint32_t r,
-                                             const uint32_t *tg, const uint32_t *fp, uint32_t sh, uint64_t &any,
-                                             Bits<C> &bits) {
+// The exact rolling hash over the thread's C windows, the one loop every
+// exact pass and the hash dump run: the state of the window ending before the
+// thread's first one (exact_init), then one exact_step_k per window with the
+// entering byte from w and the leaving byte from the out-stream dwords d;
+// visit(i, s) sees the lazy state s of window i (congruent to its hash,
+// s < 2^62 + 2^11).
+template <int C, int OUTK, typename Visit>
+__device__ __forceinline__ void roll_exact(const uint32_t *w, const uint32_t *d, OutStream os, uint32_t m, uint32_t r,
+                                           Visit &&visit) {
   uint64_t s = exact_init(w, m);
-  uint32_t dlo = d[0], ow = 0, acc = 0;
+  uint32_t dlo = d[0], ow = 0;
 #pragma unroll
   for (int i = 0; i < C; ++i) {
     if ((i & 3) == 0) {
@@ -484,6 +489,16 @@ __device__ __forceinline__ void pass_exact_w(const uint32_t *w, const uint32_t *
       dlo = dhi;
     }
     s = exact_step_k<OUTK>(s, byte_at(w, 64 + i), (ow >> (8 * (i & 3))) & 0xFFu, r);
+    visit(i, s);
+  }
+}
+
+template <int C, bool ANY, bool TABLE, int NT, int OUTK>
+__device__ __forceinline__ void pass_exact_w(const uint32_t *w, const uint32_t *d, OutStream os, uint32_t m, uint32_t r,
+                                             const uint32_t *tg, const uint32_t *fp, uint32_t sh, uint64_t &any,
+                                             Bits<C> &bits) {
+  uint32_t acc = 0;
+  roll_exact<C, OUTK>(w, d, os, m, r, [&](int i, uint64_t s) __attribute__((always_inline)) {
     if (TABLE) {
       const bool c = in_cuckoo(fp, sh, (uint32_t)canon(s));
       if (ANY) any_or(any, ballot(c));
@@ -501,7 +516,7 @@ __device__ __forceinline__ void pass_exact_w(const uint32_t *w, const uint32_t *
         put_bit<C>(bits, acc, i, c);
       }
     }
-  }
+  });
 }
 
 template <int C, bool ANY, bool TABLE, int NT, int OUTK, bool PRE>
@@ -528,38 +543,54 @@ __device__ __forceinline__ void pass_exact_r(const uint32_t *tw, OutStream os, u
   else pass_exact<C, ANY, TABLE, NT, 2, PRE>(tw, os, m, r, tg, fp, sh, any, bits, pre);
 }
 
-// kDump: canonical rolling hash of windows x = e - m + 1 with x % stride == 0.
-template <int C>
-__device__ __forceinline__ void pass_dump(const uint32_t *tw, OutStream os, uint32_t m, uint32_t r, int64_t e0, uint64_t n,
-                                          const ScanParams &p) {
-  uint32_t w[16 + C / 4];
-  load_words<16 + C / 4>(w, tw);
-  uint64_t s = exact_init(w, m);
+// Destination of a hash dump: the canonical hash of every window whose start
+// x = e - m + 1 is a multiple of stride goes to out[x / stride] (x / stride < cap).
+struct DumpDst {
+  uint64_t *out;
+  uint64_t stride;
+  uint64_t cap;
+};
+
+// kDump: the exact pass's own rolling loop (roll_exact, same out-kind
+// specialisation as the test passes), writing canonical states of sampled
+// windows instead of testing them.
+template <int C, int OUTK>
+__device__ __forceinline__ void pass_dump_w(const uint32_t *w, const uint32_t *d, OutStream os, uint32_t m, uint32_t r,
+                                            int64_t e0, uint64_t n, const DumpDst &dst) {
   const int64_t x0 = e0 - (int64_t)m + 1;
   // rem = x0 mod stride for the first window (x0 may be negative)
-  const int64_t st = (int64_t)p.dump_stride;
+  const int64_t st = (int64_t)dst.stride;
   int64_t rem = x0 % st;
   if (rem < 0) rem += st;
   // slot of the next sampled window at or after x0 (x0 - rem is a multiple of st)
   int64_t slot = (x0 - rem) / st + (rem ? 1 : 0);
-  uint32_t d[C / 4 + 1];
-  load_words<C / 4 + 1>(d, os.d);
-  uint32_t dlo = d[0], ow = 0;
-#pragma unroll
-  for (int i = 0; i < C; ++i) {
-    if ((i & 3) == 0) {
-      const uint32_t dhi = d[(i >> 2) + 1];
-      ow = __builtin_amdgcn_alignbyte(dhi, dlo, os.sh);
-      dlo = dhi;
-    }
-    s = exact_step(s, byte_at(w, 64 + i), (ow >> (8 * (i & 3))) & 0xFFu, r);
+  roll_exact<C, OUTK>(w, d, os, m, r, [&](int i, uint64_t s) __attribute__((always_inline)) {
     const int64_t x = x0 + i;
     if (rem == 0) {
-      if (x >= 0 && (uint64_t)x + m <= n && (uint64_t)slot < p.dump_cap) p.dump_out[slot] = canon(s);
+      if (x >= 0 && (uint64_t)x + m <= n && (uint64_t)slot < dst.cap) dst.out[slot] = canon(s);
       ++slot;
     }
     rem = (rem + 1 == st) ? 0 : rem + 1;
+  });
+}
+
+// The dump of one tile for the thread: words from registers (pre) or the LDS tile.
+template <int C, bool PRE>
+__device__ __forceinline__ void pass_dump(const uint32_t *tw, OutStream os, uint32_t m, uint32_t r, int64_t e0, uint64_t n,
+                                          const DumpDst &dst, const PreWords<C> *pre) {
+  uint32_t wl[PRE ? 1 : 16 + C / 4], dl[PRE ? 1 : C / 4 + 1];
+  const uint32_t *w = wl, *d = dl;
+  if constexpr (PRE) {
+    w = pre->w;
+    d = pre->d;
+  } else {
+    load_words<16 + C / 4>(wl, tw);
+    load_words<C / 4 + 1>(dl, os.d);
   }
+  const int k = out_kind(r);
+  if (k == 0) pass_dump_w<C, 0>(w, d, os, m, r, e0, n, dst);
+  else if (k == 1) pass_dump_w<C, 1>(w, d, os, m, r, e0, n, dst);
+  else pass_dump_w<C, 2>(w, d, os, m, r, e0, n, dst);
 }
 
 // Runs the test pass of bucket D over the thread's windows: ANY=true ORs the
@@ -691,20 +722,51 @@ __device__ __forceinline__ bool window_equals(const uint8_t *end, const uint8_t 
   return true;
 }
 
+// Compares the m bytes at a (device memory: the text, any alignment) with the
+// pattern at pat (device memory, 4-byte aligned), four bytes per step; reads
+// only the text dwords that hold bytes of [a, a + m).  For windows longer than
+// the tile's front halo.
+__device__ __forceinline__ bool window_equals_global(const uint8_t *a, const uint8_t *pat, uint32_t m) {
+  const uint32_t mis = (uint32_t)(uintptr_t)a & 3u;
+  const uint32_t *aw = (const uint32_t *)(a - mis);
+  const uint32_t *pw = (const uint32_t *)pat;
+  const uint32_t nd = (mis + m + 3u) >> 2;  // dwords holding window bytes
+  uint32_t lo = aw[0];
+  for (uint32_t q = 0; 4 * q < m; ++q) {
+    const uint32_t hi = q + 1 < nd ? aw[q + 1] : 0u;  // bytes past the window are masked below
+    const uint32_t rem = m - 4 * q;
+    const uint32_t keep = rem >= 4 ? 0xFFFFFFFFu : ((1u << (8 * rem)) - 1u);
+    if ((__builtin_amdgcn_alignbyte(hi, lo, mis) ^ pw[q]) & keep) return false;
+    lo = hi;
+  }
+  return true;
+}
+
+// Whether the pattern referenced by om (om_pack) occurs as the window ending
+// at *end (LDS tile; global end index e): the window must start inside the
+// text and its bytes must equal the pattern's (the byte comparison of Sec. 3.1
+// that follows every hash hit).  Windows that reach beyond the tile's front
+// halo (patterns longer than kFront) are compared in the text itself (gtext).
+__device__ __forceinline__ bool entry_matches(const uint8_t *gimg, const BucketDesc &D, uint32_t om,
+                                              const uint8_t *end, int64_t e, const uint8_t *gtext) {
+  const uint32_t m = om_len(om);
+  const int64_t x = e - (int64_t)m + 1;
+  if (x < 0) return false;
+  const uint8_t *pat = gimg + D.pat_off + om_off(om);
+  if (m <= kFront) return window_equals(end, pat, m);
+  return window_equals_global(gtext + x, pat, m);
+}
+
 // Verifies the entries of a record (slot_inline / slot_run) for the candidate
-// window ending at *end (global end index e): an entry matches when its window
-// starts inside the text and its bytes equal the window's (the byte comparison
-// of Sec. 3.1 that follows every hash hit).  Consecutive entries with the same
-// pattern bytes (identical patterns under several ids) share one comparison.
-// Returns the number of matching entries; bit i of mask is set for a matching
-// entry i < 32 of the run.
+// window ending at *end (global end index e).  Consecutive entries with the
+// same pattern bytes (identical patterns under several ids) share one
+// comparison.  Returns the number of matching entries; bit i of mask is set
+// for a matching entry i < 32 of the run.
 __device__ __forceinline__ uint32_t verify_run(const uint8_t *gimg, const BucketDesc &D, uint64_t rec, const uint8_t *end,
-                                               int64_t e, uint32_t &mask) {
+                                               int64_t e, const uint8_t *gtext, uint32_t &mask) {
   mask = 0;
   if (rec >> 63) {
-    const uint32_t om = (uint32_t)rec, m = om >> 24;
-    const bool ok = e - (int64_t)m + 1 >= 0 && window_equals(end, gimg + D.pat_off + (om & 0xFFFFFFu), m);
-    mask = ok ? 1u : 0u;
+    mask = entry_matches(gimg, D, (uint32_t)rec, end, e, gtext) ? 1u : 0u;
     return mask;
   }
   const Entry *ent = (const Entry *)(gimg + D.ent_off);
@@ -714,8 +776,7 @@ __device__ __forceinline__ uint32_t verify_run(const uint8_t *gimg, const Bucket
   for (uint32_t i = 0; i < cnt; ++i) {
     const uint32_t om = ent[first + i].off_m;
     if (om != prev) {
-      const uint32_t m = om >> 24;
-      prev_ok = e - (int64_t)m + 1 >= 0 && window_equals(end, gimg + D.pat_off + (om & 0xFFFFFFu), m);
+      prev_ok = entry_matches(gimg, D, om, end, e, gtext);
       prev = om;
     }
     if (prev_ok) {
@@ -728,13 +789,16 @@ __device__ __forceinline__ uint32_t verify_run(const uint8_t *gimg, const Bucket
 
 // Writes the matching entries of a verified record as hit records
 // (pid << 40 | start) at slab[o..], up to cap; o advances over all of them.
+// pid_counts (optional): per-pattern hit counters, one increment per hit.
 __device__ __forceinline__ void write_hits(const uint8_t *gimg, const BucketDesc &D, uint64_t rec, uint32_t mask,
-                                           const uint8_t *end, int64_t e, uint64_t *slab, uint32_t cap, uint32_t &o) {
+                                           const uint8_t *end, int64_t e, const uint8_t *gtext, uint64_t *slab,
+                                           uint32_t cap, uint32_t &o, unsigned long long *pid_counts) {
   if (rec >> 63) {
     if (mask) {
       const uint32_t om = (uint32_t)rec, pid = (uint32_t)(rec >> 32) & 0xFFFFFFu;
-      const uint64_t x = (uint64_t)(e - (int64_t)(om >> 24) + 1);
+      const uint64_t x = (uint64_t)(e - (int64_t)om_len(om) + 1);
       if (o < cap) slab[o] = ((uint64_t)pid << kPosBits) | x;
+      if (pid_counts) atomicAdd(pid_counts + pid, 1ull);
       ++o;
     }
     return;
@@ -743,16 +807,11 @@ __device__ __forceinline__ void write_hits(const uint8_t *gimg, const BucketDesc
   const uint32_t first = (uint32_t)rec, cnt = (uint32_t)(rec >> 32);
   for (uint32_t i = 0; i < cnt; ++i) {
     const Entry en = ent[first + i];
-    bool hit;
-    if (i < 32) {
-      hit = (mask >> i) & 1u;
-    } else {
-      const uint32_t m = en.off_m >> 24;
-      hit = e - (int64_t)m + 1 >= 0 && window_equals(end, gimg + D.pat_off + (en.off_m & 0xFFFFFFu), m);
-    }
+    const bool hit = i < 32 ? ((mask >> i) & 1u) != 0 : entry_matches(gimg, D, en.off_m, end, e, gtext);
     if (!hit) continue;
-    const uint64_t x = (uint64_t)(e - (int64_t)(en.off_m >> 24) + 1);
+    const uint64_t x = (uint64_t)(e - (int64_t)om_len(en.off_m) + 1);
     if (o < cap) slab[o] = ((uint64_t)en.pid << kPosBits) | x;
+    if (pid_counts) atomicAdd(pid_counts + en.pid, 1ull);
     ++o;
   }
 }
@@ -809,7 +868,8 @@ __device__ __forceinline__ void candidate_phase(Bits<C> &bits, const BucketDesc 
                                                 uint64_t n, int64_t e0, const uint8_t *img, const uint8_t *gimg,
                                                 uint32_t *cand,
                                                 uint32_t *misc, uint64_t *slab, uint32_t cap, uint32_t &tile_hits,
-                                                uint32_t &ncand, uint64_t rec1 = 0) {
+                                                uint32_t &ncand, const uint8_t *gtext,
+                                                unsigned long long *pid_counts, uint64_t rec1 = 0) {
   constexpr uint32_t W = WG * C;
   constexpr int NB = (C + 31) / 32;
   const uint32_t tid = threadIdx.x;
@@ -875,13 +935,13 @@ __device__ __forceinline__ void candidate_phase(Bits<C> &bits, const BucketDesc 
                                       : horner_exact(end - (m - 1), m);
           rec = table ? table_record(img, gimg, D, (uint32_t)key) : key_lookup(gimg, D, key);
         }
-        nh = verify_run(gimg, D, rec, end, e, hmask);
+        nh = verify_run(gimg, D, rec, end, e, gtext, hmask);
       }
       uint32_t nht;
       const uint32_t hb = block_excl_scan<WG>(nh, misc, nht);
       if (nh) {
         uint32_t o = tile_hits + hb;
-        write_hits(gimg, D, rec, hmask, end, e, slab, cap, o);
+        write_hits(gimg, D, rec, hmask, end, e, gtext, slab, cap, o, pid_counts);
       }
       tile_hits += nht;
     }
@@ -1034,7 +1094,7 @@ __global__ __launch_bounds__(WG) void scan_kernel(ScanParams p) {
         const OutStream os = out_stream(mine, m);
         if constexpr (FAM == kFamExact) {
           if (D.kind == kDump) {
-            pass_dump<C>(tw, os, m, r, e0, n, p);
+            pass_dump<C, false>(tw, os, m, r, e0, n, DumpDst{p.dump_out, p.dump_stride, p.dump_cap}, nullptr);
             continue;
           }
         }
@@ -1070,7 +1130,8 @@ __global__ __launch_bounds__(WG) void scan_kernel(ScanParams p) {
         uint64_t dummy = 0;
         run_pass<C, false, FAM>(D, tw, os, r, (const uint32_t *)(img + D.fp_off), dummy, bits);
         uint32_t ncand;
-        candidate_phase<WG, C>(bits, D, tile, tstart, n, e0, img, gimg, cand, misc, slab, cap, tile_hits, ncand);
+        candidate_phase<WG, C>(bits, D, tile, tstart, n, e0, img, gimg, cand, misc, slab, cap, tile_hits, ncand,
+                               cur.text, p.direct ? nullptr : p.pid_counts);
         if (b < 32) dense_mask = ncand >= kDenseCand ? (dense_mask | (1u << b)) : (dense_mask & ~(1u << b));
       }
     }
@@ -1132,6 +1193,15 @@ __global__ __launch_bounds__(WG) void scan_list_kernel(ListParams p) {
     if constexpr (FAM == kFamExact) load_words<C / 4 + 1>(pre.d, os.d);
     if (nt < p.ntiles) dma_tile<WG, C>(lds + (slot ^ 1u) * TILE_LDS, p.text, p.n, (int64_t)(nt * W));
     const int64_t e0 = tstart + (int64_t)(tid * C);
+    if constexpr (FAM == kFamExact) {
+      if (D.kind == kDump) {
+        // hash dump: this kernel's own rolling loop over the words read above
+        pass_dump<C, true>(tw, os, m, r, e0, p.n, DumpDst{p.dump_out, p.dump_stride, p.dump_cap}, &pre);
+        t = nt;
+        slot ^= 1u;
+        continue;
+      }
+    }
     uint32_t tile_hits = 0;
     bool run2 = dense;
     if (!dense) {
@@ -1155,7 +1225,8 @@ __global__ __launch_bounds__(WG) void scan_list_kernel(ListParams p) {
       run_pass<C, false, FAM, true>(D, tw, os, r, nullptr, dummy, bits, &pre);
       uint32_t ncand;
       candidate_phase<WG, C>(bits, D, tile, tstart, p.n, e0, nullptr, p.gimg, cand, misc,
-                             p.out + t * (uint64_t)p.slab_cap, p.slab_cap, tile_hits, ncand, p.rec1);
+                             p.out + t * (uint64_t)p.slab_cap, p.slab_cap, tile_hits, ncand, p.text, p.pid_counts,
+                             p.rec1);
       dense = ncand >= kDenseCand;
     }
     if (tid == 0) {
@@ -1191,15 +1262,6 @@ static hipError_t launch_list_t(const ListParams &p, uint32_t grid, hipStream_t 
   return hipGetLastError();
 }
 
-template <int WG, int C, int FAM>
-static hipError_t prepare_t() {
-  hipError_t e = hipFuncSetAttribute((const void *)scan_kernel<WG, C, FAM>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-  const hipError_t e2 = hipFuncSetAttribute((const void *)scan_list_kernel<WG, C, FAM>,
-                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-  return e != hipSuccess ? e : e2;
-}
-
 // Geometry CFG of kTileCfgs as template arguments.
 template <int CFG>
 struct Geom {
@@ -1227,7 +1289,24 @@ hipError_t ScanGeom<FAM, CFG>::list(const ListParams *p, uint32_t grid, hipStrea
 
 template <int FAM, int CFG>
 hipError_t ScanGeom<FAM, CFG>::prepare() {
-  return prepare_t<Geom<CFG>::WG, Geom<CFG>::C, FAM>();
+  return hipFuncSetAttribute((const void *)scan_kernel<Geom<CFG>::WG, Geom<CFG>::C, FAM>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
 }
+
+template <int FAM, int CFG>
+hipError_t ScanGeom<FAM, CFG>::list_prepare() {
+  return hipFuncSetAttribute((const void *)scan_list_kernel<Geom<CFG>::WG, Geom<CFG>::C, FAM>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+}
+
+// Explicit instantiation of the general kernel's launchers (X = launch) or
+// the single-bucket kernel's (X = list) for family FAM and geometry CFG.
+#define RK_INSTANTIATE_SCAN(FAM, CFG)                                                                     \
+  template hipError_t ScanGeom<FAM, CFG>::launch(const ScanParams &, uint32_t, uint32_t, hipStream_t); \
+  template hipError_t ScanGeom<FAM, CFG>::occupancy(uint32_t, int *);                                   \
+  template hipError_t ScanGeom<FAM, CFG>::prepare();
+#define RK_INSTANTIATE_LIST(FAM, CFG)                                                                    \
+  template hipError_t ScanGeom<FAM, CFG>::list(const ListParams *, uint32_t, hipStream_t, int *);      \
+  template hipError_t ScanGeom<FAM, CFG>::list_prepare();
 
 }  // namespace rk

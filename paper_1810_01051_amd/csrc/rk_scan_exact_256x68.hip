@@ -1,8 +1,8 @@
-// Scan kernels of the exact family (d = 256, q = 2^61 - 1; hash dump) for the
-// 256x68 tile geometry (workgroup size x windows per thread); one geometry per
-// translation unit, so that the exact kernels compile in parallel.
+// Exact family (d = 256, q = 2^61 - 1; hash dump), general scan kernel, tile geometry
+// 256x68 (workgroup size x windows per thread): one kernel per translation unit,
+// so that the exact kernels compile in parallel.
 #include "rk_scan.h"
 
 namespace rk {
-template struct ScanGeom<kFamExact, 0>;
+RK_INSTANTIATE_SCAN(kFamExact, 0)
 }  // namespace rk

@@ -9,11 +9,12 @@
 // identical patterns of one step share their bytes in the table image).  It
 // builds a batch plan for the corpus and enqueues the count pass.  When a slot's count is done the step is admitted
 // once the output arena can hold its hits; a step that could never fit is
-// split and counted again.  Then the collect pass writes the sorted hits and
+// split and counted again, and a step that finds the arena held by unreleased
+// results with nothing else in flight waits a bounded time, then fails.  Then the collect pass writes the sorted hits and
 // the per-pattern offsets come back to pinned host memory.  Count and collect
-// launches are captured into HIP graphs per slot and replayed with each
-// step's parameters (hipGraphExecUpdate; re-instantiated when the launch
-// sequence changes).
+// launches of each step are captured into a graph that updates the slot's
+// executable graph in place (hipGraphExecUpdate; re-instantiated when the
+// launch sequence changes) and launched as one unit.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -135,6 +136,7 @@ struct Slot {
   uint64_t pos_off = 0, pos_size = 0;  // merged positions of the step (arena)
   uint64_t aux_off = 0, aux_size = 0;  // per-pattern offsets and sort work (arena)
   double t_start = 0;
+  double wait_since = 0;               // counted step waiting for arena space with nothing else in flight
 };
 
 static double now_s() {
@@ -190,6 +192,16 @@ static void finish_request(rk_server *S, Request *r, rk_status st) {
   } else {
     ++S->failed;
   }
+}
+
+// A failed allocation is RK_ENOMEM (the step can be retried smaller), any
+// other HIP error RK_EDEVICE.
+static rk_status alloc_err(rk_ctx *ctx, hipError_t e, const char *what) {
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {
+    (void)hipGetLastError();
+    return set_err(ctx, RK_ENOMEM, "%s: out of memory", what);
+  }
+  return hip_err(ctx, e, what);
 }
 
 static hipError_t ensure_dev(void **p, uint64_t *cap, uint64_t need) {
@@ -350,7 +362,7 @@ static rk_status start_step(rk_server *S, Slot &sl, std::unique_lock<std::mutex>
     hipError_t e = ensure_dev(&sl.dplan, &sl.dplan_cap, bb + db + ib);
     if (e == hipSuccess) e = ensure_pinned(&sl.hstage, &sl.hstage_cap, bb + db + ib);
     if (regrow) drop_graphs(sl);  // captured addresses changed
-    if (e != hipSuccess) st = hip_err(S->ctx, e, "step plan buffers");
+    if (e != hipSuccess) st = alloc_err(S->ctx, e, "step plan buffers");
   }
   // Staging records per tile, from the expected hits per tile (a tile with
   // more is rescanned by the collect pass, a whole extra scan for the dense
@@ -375,7 +387,7 @@ static rk_status start_step(rk_server *S, Slot &sl, std::unique_lock<std::mutex>
     const bool regrow = L.total > sl.scratch_cap;
     hipError_t e = ensure_dev(&sl.scratch, &sl.scratch_cap, L.total);
     if (regrow) drop_graphs(sl);
-    if (e != hipSuccess) st = hip_err(S->ctx, e, "step scratch");
+    if (e != hipSuccess) st = alloc_err(S->ctx, e, "step scratch");
   }
   if (st == RK_OK) {
     memset(sl.hstage, 0, bb + db + ib);
@@ -391,7 +403,7 @@ static rk_status start_step(rk_server *S, Slot &sl, std::unique_lock<std::mutex>
     st = run_maybe_graph(S, sl, &sl.gcount, [&]() -> rk_status {
       hipError_t e = hipMemcpyAsync(sl.dplan, sl.hstage, sl.plan_bytes, hipMemcpyHostToDevice, sl.stream);
       if (e != hipSuccess) return hip_err(S->ctx, e, "plan upload");
-      rk_status s2 = count_enqueue(S->ctx, &sl.plan, nullptr, 0, sl.scratch, sl.scratch_cap, sl.stream);
+      rk_status s2 = count_enqueue(S->ctx, &sl.plan, nullptr, 0, sl.scratch, sl.scratch_cap, nullptr, sl.stream);
       if (s2 != RK_OK) return s2;
       e = hipMemcpyAsync(sl.hctr, sl.scratch, 16, hipMemcpyDeviceToHost, sl.stream);
       return e == hipSuccess ? RK_OK : hip_err(S->ctx, e, "count readback");
@@ -402,6 +414,14 @@ static rk_status start_step(rk_server *S, Slot &sl, std::unique_lock<std::mutex>
     if (e != hipSuccess) st = hip_err(S->ctx, e, "event");
   }
   lk.lock();
+  if (st == RK_ENOMEM && take.size() > 1) {
+    // not enough memory for a step this large: its requests go back to the
+    // front of the queue and later steps take half as many
+    for (auto it = take.rbegin(); it != take.rend(); ++it) S->pending.push_front(*it);
+    S->step_limit = (uint32_t)std::max<size_t>(1, take.size() / 2);
+    ++S->step_splits;
+    return st;
+  }
   if (st != RK_OK) {
     for (Request *r : take) finish_request(S, r, st);
     S->cv_done.notify_all();
@@ -561,8 +581,30 @@ static void scheduler(rk_server *S) {
         }
       }
       if (sl.state == kCounted) {
-        if (try_collect(S, sl, lk)) progress = true;
-        else ++S->admission_waits;
+        if (try_collect(S, sl, lk)) {
+          sl.wait_since = 0;
+          progress = true;
+        } else {
+          // No room in the arena.  Steps in flight free their sort work when
+          // their collect ends; with none in flight only the client's
+          // releases can make room, so the wait is bounded.
+          bool others = false;
+          for (Slot &o : S->slots) others |= &o != &sl && (o.state == kCounting || o.state == kCollecting);
+          const double t = now_s();
+          if (sl.wait_since == 0) ++S->admission_waits;
+          if (others || sl.wait_since == 0) {
+            sl.wait_since = t;
+          } else if (t - sl.wait_since > S->cfg.admission_timeout_s) {
+            fail_step(S, sl, set_err(S->ctx, RK_ENOSPACE,
+                                     "no arena space for a step of %llu hits for %.3f s with no step in flight: "
+                                     "unreleased results hold %llu of %llu bytes",
+                                     (unsigned long long)sl.total, S->cfg.admission_timeout_s,
+                                     (unsigned long long)S->arena.used, (unsigned long long)S->arena.cap));
+            sl.wait_since = 0;
+            S->cv_done.notify_all();
+            progress = true;
+          }
+        }
       }
       if (sl.state == kCollecting) {
         const hipError_t q = hipEventQuery(sl.ev_collect);
@@ -575,6 +617,17 @@ static void scheduler(rk_server *S) {
       }
     }
     if (S->stop && S->inflight == 0) break;
+    if (S->cfg.request_timeout_s > 0 && !S->pending.empty()) {
+      // requests that waited too long for a step (the oldest are in front)
+      const double t = now_s();
+      bool any = false;
+      while (!S->pending.empty() && t - S->pending.front()->t_submit > S->cfg.request_timeout_s) {
+        finish_request(S, S->pending.front(), RK_ETIMEDOUT);
+        S->pending.pop_front();
+        any = true;
+      }
+      if (any) S->cv_done.notify_all();
+    }
     if (!S->stop) {
       for (Slot &sl : S->slots) {
         if (sl.state != kIdle || S->pending.empty()) continue;
@@ -610,6 +663,8 @@ void rk_server_cfg_default(rk_server_cfg *cfg) {
   cfg->max_step_patterns = 1024;
   cfg->mode = RK_MODE_SCREEN;
   cfg->use_graphs = 1;
+  cfg->admission_timeout_s = 2.0;
+  cfg->request_timeout_s = 0.0;
 }
 
 rk_status rk_server_create(rk_ctx *ctx, const rk_server_cfg *cfg_in, rk_server **out) {
@@ -622,6 +677,8 @@ rk_status rk_server_create(rk_ctx *ctx, const rk_server_cfg *cfg_in, rk_server *
   if (cfg.max_step_requests < 1 || cfg.max_step_patterns < 1) return set_err(ctx, RK_EINVAL, "step limits must be >= 1");
   if (cfg.mode == RK_MODE_AUTO) cfg.mode = RK_MODE_SCREEN;
   if (cfg.mode != RK_MODE_SCREEN && cfg.mode != RK_MODE_EXACT) return set_err(ctx, RK_EINVAL, "unknown mode");
+  if (!(cfg.admission_timeout_s >= 0) || !(cfg.request_timeout_s >= 0))
+    return set_err(ctx, RK_EINVAL, "timeouts must be >= 0");
   rk_server *S = new (std::nothrow) rk_server();
   if (!S) return RK_ENOMEM;
   S->cfg = cfg;

@@ -47,7 +47,7 @@ static rk_status time_one(rk_ctx *ctx, int mode, int cfg, const uint8_t *text, u
     return set_err(ctx, RK_ENOMEM, "autotune buffers");
   }
   uint64_t total = 0;
-  st = rk_count(ctx, plan, text, n, scratch.p, sb, &total, nullptr);
+  st = rk_count(ctx, plan, text, n, scratch.p, sb, nullptr, &total, nullptr);
   if (st == RK_OK && pos.alloc(total * 8 + 8) != hipSuccess) st = set_err(ctx, RK_ENOMEM, "autotune output");
   if (st == RK_OK)
     st = rk_collect(ctx, plan, text, n, scratch.p, sb, nullptr, 0, (uint64_t *)offd.p, (uint64_t *)pos.p, total,
@@ -61,7 +61,7 @@ static rk_status time_one(rk_ctx *ctx, int mode, int cfg, const uint8_t *text, u
     const bool prof = ctx->profile;
     rk_ctx_profile_reset(ctx);
     ctx->profile = true;
-    for (int rep = 0; rep < 6 && st == RK_OK; ++rep) st = rk_count(ctx, plan, text, n, scratch.p, sb, &total, nullptr);
+    for (int rep = 0; rep < 6 && st == RK_OK; ++rep) st = rk_count(ctx, plan, text, n, scratch.p, sb, nullptr, &total, nullptr);
     double best = 1e30;
     for (auto &ev : ctx->prof_events) {
       if (ev.kind != 0) continue;

@@ -104,15 +104,60 @@ class Context:
               "rk_window_hashes")
         return out
 
-    def scan_dump(self, text: torch.Tensor, m: int, stride: int, stream=None) -> torch.Tensor:
-        """Hashes of windows x = 0, stride, 2*stride, ... taken from the scan's rolling state."""
+    def scan_dump(self, text: torch.Tensor, m: int, stride: int, kernel: int = 0, stream=None) -> torch.Tensor:
+        """Hashes of windows x = 0, stride, 2*stride, ... taken from a scan
+        kernel's rolling state (kernel 0: the general scan kernel, 1: the
+        single-bucket kernel of one-pattern searches)."""
         n = text.numel()
         cnt = 0 if n < m else (n - m) // stride + 1
         out = torch.full((max(cnt, 1),), -1, dtype=torch.int64, device=text.device)
         check(self.lib.rk_scan_dump(self.h, ctypes.c_void_p(text.data_ptr()), n, int(m), int(stride),
-                                    ctypes.c_void_p(out.data_ptr()), out.numel(), _stream_handle(stream)), self.h,
-              "rk_scan_dump")
+                                    ctypes.c_void_p(out.data_ptr()), out.numel(), int(kernel),
+                                    _stream_handle(stream)), self.h, "rk_scan_dump")
         return out[:cnt]
+
+    def paper_search(self, text: torch.Tensor, pattern: bytes, threads_per_block: int = 1024, hashes: bool = False,
+                     stream=None):
+        """The paper's GPU procedure (rk_paper_search): returns the result
+        byte array (n - m + 1 entries, 1 at every match) and, with hashes,
+        every window's 32-bit shift-add hash (int64 tensor)."""
+        pattern = bytes(pattern)
+        m = len(pattern)
+        n = text.numel()
+        nwin = max(n - m + 1, 0)
+        flags = torch.empty(max(nwin, 1), dtype=torch.uint8, device=text.device)
+        hs = torch.empty(max(nwin, 1), dtype=torch.int32, device=text.device) if hashes else None
+        pat_host = np.frombuffer(pattern, np.uint8).copy() if m else np.zeros(1, np.uint8)
+        pat_dev = torch.from_numpy(pat_host).to(text.device)
+        check(self.lib.rk_paper_search(self.h, ctypes.c_void_p(text.data_ptr()), n,
+                                       ctypes.c_void_p(pat_dev.data_ptr()), pat_host.ctypes.data_as(ctypes.c_void_p),
+                                       m, int(threads_per_block), ctypes.c_void_p(flags.data_ptr()),
+                                       ctypes.c_void_p(hs.data_ptr()) if hs is not None else None,
+                                       _stream_handle(stream)), self.h, "rk_paper_search")
+        flags = flags[:nwin]
+        if hashes:
+            return flags, (hs[:nwin].to(torch.int64) & 0xFFFFFFFF)
+        return flags
+
+    def paper_positions(self, flags: torch.Tensor, stream=None) -> torch.Tensor:
+        """Ascending positions of the nonzero bytes of a paper-mode result array."""
+        nf = flags.numel()
+        b = ctypes.c_uint64()
+        check(self.lib.rk_paper_scratch_size(nf, ctypes.byref(b)), None, "rk_paper_scratch_size")
+        scratch = torch.empty(max(int(b.value), 256), dtype=torch.uint8, device=flags.device)
+        tot = ctypes.c_uint64()
+        cap = 1 << 16
+        while True:
+            pos = torch.empty(cap, dtype=torch.int64, device=flags.device)
+            st = self.lib.rk_paper_positions(self.h, ctypes.c_void_p(flags.data_ptr()), nf,
+                                             ctypes.c_void_p(scratch.data_ptr()), scratch.numel(),
+                                             ctypes.c_void_p(pos.data_ptr()), cap, ctypes.byref(tot),
+                                             _stream_handle(stream))
+            if st == _lib.RK_ENOSPACE and tot.value > cap:
+                cap = int(tot.value)
+                continue
+            check(st, self.h, "rk_paper_positions")
+            return pos[:int(tot.value)]
 
 
 class Plan:
@@ -158,13 +203,19 @@ class Plan:
             self._scratch = torch.empty(max(need, 256), dtype=torch.uint8, device=device)
         return self._scratch
 
-    def count(self, text: torch.Tensor, scratch: torch.Tensor | None = None, stream=None) -> int:
+    def count(self, text: torch.Tensor, scratch: torch.Tensor | None = None, stream=None,
+              counts: torch.Tensor | None = None) -> int:
+        """Count pass; returns the total.  counts (optional, k int64 on the
+        device) receives each pattern's number of occurrences."""
         if scratch is None:
             scratch = self.scratch(text.numel(), text.device)
+        if counts is not None and (counts.dtype != torch.int64 or counts.numel() < self.k or not counts.is_contiguous()):
+            raise ValueError("counts must be a contiguous int64 tensor of k entries")
         tot = ctypes.c_uint64()
         check(self.lib.rk_count(self.ctx.h, self.h, ctypes.c_void_p(text.data_ptr()), text.numel(),
-                                ctypes.c_void_p(scratch.data_ptr()), scratch.numel(), ctypes.byref(tot),
-                                _stream_handle(stream)), self.ctx.h, "rk_count")
+                                ctypes.c_void_p(scratch.data_ptr()), scratch.numel(),
+                                ctypes.c_void_p(counts.data_ptr()) if counts is not None else None,
+                                ctypes.byref(tot), _stream_handle(stream)), self.ctx.h, "rk_count")
         return int(tot.value)
 
     def collect(self, text: torch.Tensor, total: int, scratch: torch.Tensor | None = None,
@@ -190,6 +241,28 @@ class Plan:
         """Returns (offsets int64[k+1], positions int64[total]) on the device."""
         total = self.count(text, stream=stream)
         return self.collect(text, total, stream=stream)
+
+    def search_host(self, text, piece_bytes: int = 256 << 20):
+        """Streamed search of a text in host memory (numpy uint8 / bytes) or a
+        file (str path), of any length: returns (offsets, positions) as numpy
+        uint64 arrays in host memory."""
+        res = ctypes.POINTER(_lib.RkHostResult)()
+        if isinstance(text, str):
+            st = self.lib.rk_search_file(self.ctx.h, self.h, text.encode(), int(piece_bytes), ctypes.byref(res))
+        else:
+            a = np.ascontiguousarray(np.frombuffer(text, np.uint8) if isinstance(text, (bytes, bytearray)) else text,
+                                     dtype=np.uint8)
+            st = self.lib.rk_search_host(self.ctx.h, self.h, a.ctypes.data_as(ctypes.c_void_p) if a.size else None,
+                                         a.size, int(piece_bytes), ctypes.byref(res))
+        check(st, self.ctx.h, "rk_search_host")
+        r = res.contents
+        try:
+            offsets = np.ctypeslib.as_array(r.offsets, shape=(r.k + 1,)).copy()
+            positions = (np.ctypeslib.as_array(r.positions, shape=(r.total,)).copy() if r.total
+                         else np.zeros(0, np.uint64))
+        finally:
+            self.lib.rk_host_result_free(res)
+        return offsets, positions
 
 
 def check_text(text: torch.Tensor):
@@ -277,7 +350,7 @@ class BatchPlan:
         sc = self._scratch
         tot = ctypes.c_uint64()
         check(self.lib.rk_count(self.ctx.h, self.h, None, self.n_total, ctypes.c_void_p(sc.data_ptr()), sc.numel(),
-                                ctypes.byref(tot), _stream_handle(stream)), self.ctx.h, "rk_count(batch)")
+                                None, ctypes.byref(tot), _stream_handle(stream)), self.ctx.h, "rk_count(batch)")
         total = int(tot.value)
         wb = ctypes.c_uint64()
         check(self.lib.rk_work_size(self.ctx.h, self.h, total, ctypes.byref(wb)), self.ctx.h)

@@ -18,8 +18,8 @@ from .search import Context, _mode, check_text, pack_patterns
 class Server:
     def __init__(self, ctx: Context, arena_bytes: int = 1 << 30, max_inflight: int = 2,
                  max_step_requests: int = None, max_step_patterns: int = None, mode="screen",
-                 use_graphs: bool = True):
-        """Step limits left at None keep the library's defaults
+                 use_graphs: bool = True, admission_timeout_s: float = None, request_timeout_s: float = None):
+        """Limits left at None keep the library's defaults
         (rk_server_cfg_default)."""
         self.ctx = ctx
         self.lib = ctx.lib
@@ -33,6 +33,10 @@ class Server:
             cfg.max_step_patterns = int(max_step_patterns)
         cfg.mode = _mode(mode)
         cfg.use_graphs = 1 if use_graphs else 0
+        if admission_timeout_s is not None:
+            cfg.admission_timeout_s = float(admission_timeout_s)
+        if request_timeout_s is not None:
+            cfg.request_timeout_s = float(request_timeout_s)
         h = ctypes.c_void_p()
         check(self.lib.rk_server_create(ctx.h, ctypes.byref(cfg), ctypes.byref(h)), ctx.h, "rk_server_create")
         self.h = h

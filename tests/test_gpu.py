@@ -125,6 +125,13 @@ def test_config2_full_size(bench_ctx, rk, config2_full, mode):
         text = dev(s.text)
         gh = bench_ctx.window_hashes(text, 32, torch.from_numpy(xs.astype(np.int64))).cpu().numpy()
         assert gh.astype(np.uint64).tolist() == oracle.window_hashes(s.text, 32, xs).tolist()
+        # the hot-path kernel's own rolling hashes (single-bucket kernel, the
+        # tuned geometry and full grid the bench runs) of every 4099th window
+        stride = 4099
+        d = bench_ctx.scan_dump(text, 32, stride, kernel=1).cpu().numpy().astype(np.uint64)
+        xs = np.arange(0, s.text.size - 32 + 1, stride, dtype=np.uint64)
+        assert d.size == xs.size > 10 ** 6
+        assert np.array_equal(d, oracle.window_hashes(s.text, 32, xs))
 
 
 @pytest.mark.parametrize("mode", MODES)
@@ -307,19 +314,52 @@ def test_constructed_collisions_are_rejected(ctx, rk, mode):
     t = dev(text)
     for w in pats:
         m = len(w)
-        d = ctx.scan_dump(t, m, m).cpu().numpy().astype(np.uint64)
-        assert d[200] == d[1000] == np.uint64(oracle.hash(w))
+        for kernel in (0, 1):
+            d = ctx.scan_dump(t, m, m, kernel=kernel).cpu().numpy().astype(np.uint64)
+            assert d[200] == d[1000] == np.uint64(oracle.hash(w))
 
 
-@pytest.mark.parametrize("m", [1, 4, 7, 8, 9, 15, 16, 24, 31, 32, 33, 47, 61, 63, 64])
-def test_scan_dump_matches_oracle(ctx, rk, m):
-    g = rkgen.rng(53, m)
-    n = 300000 + m
+@pytest.mark.parametrize("kernel", [0, 1])
+def test_scan_dump_matches_oracle(ctx, rk, kernel):
+    """Every length 1..64 (so every out-term specialisation of the rolling
+    step: r = 8m mod 61 in the low word, in the high word, or anywhere): the
+    hashes a scan kernel's own rolling loop holds for sampled windows equal the
+    oracle's direct evaluation.  kernel 0 = general scan, 1 = single-bucket."""
+    g = rkgen.rng(53, kernel)
+    n = 300000 + 13
     text = np.frombuffer(g.bytes(n), np.uint8).copy()
-    stride = 4099
-    d = ctx.scan_dump(dev(text), m, stride).cpu().numpy().astype(np.uint64)
-    xs = np.arange(0, n - m + 1, stride, dtype=np.uint64)
-    assert d.tolist() == oracle.window_hashes(text, m, xs).tolist()
+    t = dev(text)
+    stride = 997
+    for m in range(1, 65):
+        d = ctx.scan_dump(t, m, stride, kernel=kernel).cpu().numpy().astype(np.uint64)
+        xs = np.arange(0, n - m + 1, stride, dtype=np.uint64)
+        assert d.tolist() == oracle.window_hashes(text, m, xs).tolist(), "m=%d" % m
+
+
+@pytest.mark.parametrize("kernel", [0, 1])
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3])
+def test_scan_dump_every_geometry(ctx, rk, kernel, cfg):
+    """The dump in every tile geometry with a forced small grid (each
+    workgroup walks many tiles, reusing both LDS slots), stride 1 around tile
+    seams and a ragged end: one kernel's rolling state equals direct Horner."""
+    lib = rk._lib.load()
+    wg, c, tb = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
+    lib.rk_tile_cfg(cfg, ctypes.byref(wg), ctypes.byref(c), ctypes.byref(tb))
+    W = tb.value
+    g = rkgen.rng(55, cfg)
+    n = 9 * W + 45
+    text = np.frombuffer(g.bytes(n), np.uint8).copy()
+    t = dev(text)
+    ctx.set_option(rk._lib.RK_OPT_TILE_CFG, cfg)
+    ctx.set_option(rk._lib.RK_OPT_GRID, 3)
+    try:
+        for m in (4, 7, 32, 64):
+            d = ctx.scan_dump(t, m, 1, kernel=kernel).cpu().numpy().astype(np.uint64)
+            xs = np.arange(0, n - m + 1, dtype=np.uint64)
+            assert d.tolist() == oracle.window_hashes(text, m, xs).tolist(), "m=%d" % m
+    finally:
+        ctx.set_option(rk._lib.RK_OPT_TILE_CFG, -1)
+        ctx.set_option(rk._lib.RK_OPT_GRID, 0)
 
 
 def test_window_hashes_match_oracle(ctx, rk):
@@ -352,13 +392,108 @@ def test_queue_and_grid_options(ctx, rk, mode):
         assert_same(run(ctx, rk, s.text, s.patterns, mode, opts), ref, str(opts))
 
 
+LONG = (65, 100, 200, 800, 1024)
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3])
+def test_long_patterns_seams(ctx, rk, mode, cfg):
+    """Patterns longer than the rolled window (65..1024 bytes): occurrences
+    planted across tile and thread seams, at both ends of a ragged text, and
+    overlapping; one plan with all lengths plus short ones (multi-bucket
+    kernel) and each long pattern alone (single-bucket kernel), with a small
+    grid so every workgroup walks many tiles."""
+    lib = rk._lib.load()
+    wg, c, tb = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
+    lib.rk_tile_cfg(cfg, ctypes.byref(wg), ctypes.byref(c), ctypes.byref(tb))
+    W, C = tb.value, c.value
+    g = rkgen.rng(57, cfg)
+    n = 5 * W + 1500
+    text = rkgen.iid_text(g, n, rkgen.ACGT)
+    pats = [rkgen.ACGT[g.integers(0, 4, size=m)].tobytes() for m in LONG]
+    for j, p in enumerate(pats):
+        m = len(p)
+        for base in (0, W, 2 * W + C, 4 * W, n - m):
+            for d in (-m, -m + 1, -1, 0, 1, j):
+                x = base + d
+                if 0 <= x <= n - m:
+                    text[x:x + m] = np.frombuffer(p, np.uint8)
+    # short patterns and a long one that shares the last 64 bytes of another
+    extra = [text[10:18].tobytes(), text[W - 20:W + 12].tobytes(), b"G" * 3 + pats[3][3:]]
+    opts = {rk._lib.RK_OPT_TILE_CFG: cfg, rk._lib.RK_OPT_GRID: 5}
+    allp = pats + extra
+    got = run(ctx, rk, text, allp, mode, opts)
+    ref = oracle.search(text, allp)
+    assert int(ref[0][-1]) > 10  # plants of the long patterns overwrite each other
+    assert_same(got, ref, "long cfg %d" % cfg)
+    for p in pats:
+        assert_same(run(ctx, rk, text, [p], mode, opts), oracle.search(text, [p]), "single m=%d" % len(p))
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_long_patterns_random(ctx, rk, mode):
+    """Random texts over four alphabets with mixed short and long patterns
+    (sampled and random), duplicates, runs of one byte (every window of a
+    long run matches), against the oracle."""
+    g = rkgen.rng(58, 1 if mode == "screen" else 2)
+    tables = [np.frombuffer(b"ab", np.uint8), rkgen.ACGT, rkgen.LOWER, rkgen.BYTE256]
+    for trial in range(24):
+        n = int(g.integers(0, 30000))
+        table = tables[trial % 4]
+        text = rkgen.iid_text(g, n, table)
+        if trial % 6 == 5 and n > 3000:
+            text[1000:2500] = table[0]
+        pats = []
+        for _ in range(int(g.integers(1, 12))):
+            m = int(g.choice([3, 16, 64, 65, 66, 127, 128, 300, 700, 1024]))
+            if n >= m and g.random() < 0.7:
+                o = int(g.integers(0, n - m + 1))
+                pats.append(text[o:o + m].tobytes())
+            else:
+                pats.append(rkgen.iid_text(g, m, table).tobytes())
+        if trial % 6 == 5:
+            pats += [bytes([table[0]]) * 200, bytes([table[0]]) * 1024]
+        pats += pats[:1]
+        got = run(ctx, rk, text, pats, mode)
+        assert_same(got, oracle.search(text, pats), "trial %d n=%d" % (trial, n))
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_count_per_pattern(ctx, rk, mode):
+    """rk_count's per-pattern counts equal the oracle's list lengths: a
+    multi-pattern plan (table buckets), one pattern (the single-bucket
+    kernel), a few patterns sharing register targets, duplicates, and a
+    one-slot slab (every tile with hits overflows: counts still complete)."""
+    s = rkgen.config3(n=(1 << 21) + 9, k=96, sampled=64)
+    g = rkgen.rng(56, 0)
+    cases = [(s.text, s.patterns, {}), (s.text, s.patterns[:1], {}), (s.text, s.patterns[:3] + s.patterns[:2], {}),
+             (s.text, s.patterns, {rk._lib.RK_OPT_SLAB_CAP: 1})]
+    text4 = rkgen.iid_text(g, 70000, rkgen.ACGT)
+    cases.append((text4, [text4[100:104].tobytes(), b"A", b"ACGTACGTAC"], {}))
+    for i, (text_np, pats, opts) in enumerate(cases):
+        ro, _ = oracle.search(text_np, pats, threads=4)
+        for k, v in opts.items():
+            ctx.set_option(k, v)
+        try:
+            plan = rk.Plan(ctx, pats, mode)
+            t = dev(text_np)
+            counts = torch.full((len(pats),), -5, dtype=torch.int64, device="cuda:0")
+            total = plan.count(t, counts=counts)
+            plan.close()
+        finally:
+            for k in opts:
+                ctx.set_option(k, 0)
+        assert total == int(ro[-1]), i
+        assert counts.cpu().numpy().astype(np.uint64).tolist() == np.diff(ro).tolist(), i
+
+
 def test_errors(ctx, rk):
     RkError = rk._lib.RkError
     with pytest.raises(RkError) as e:
         rk.Plan(ctx, [b""])
     assert e.value.status == rk._lib.RK_EINVAL
     with pytest.raises(RkError) as e:
-        rk.Plan(ctx, [b"a" * 65])
+        rk.Plan(ctx, [b"a" * 1025])
     assert e.value.status == rk._lib.RK_EUNSUPPORTED
     text = dev(np.zeros(4096, np.uint8))
     plan = rk.Plan(ctx, [b"\x00\x00"])
@@ -394,3 +529,47 @@ def test_batch_matches_solo_and_oracle(ctx, rk, mode):
         solo = run(ctx, rk, s.text, s.patterns, mode)
         assert_same(solo, (ro, rp), "solo %d" % i)
     bp.close()
+
+
+@pytest.fixture(scope="module")
+def config4_full():
+    """Config 4 at its full size (4,096 instances, log-uniform 4 KiB..16 MiB,
+    alphabets 4/26/256, 1..32 patterns of 4..64 bytes) with the oracle's
+    per-pattern lists of every instance (instances in parallel)."""
+    from concurrent.futures import ThreadPoolExecutor
+    insts = rkgen.config4()
+    with ThreadPoolExecutor(THREADS) as ex:
+        refs = list(ex.map(lambda s: oracle.split(*oracle.search(s.text, s.patterns)), insts))
+    return insts, refs
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_config4_full_size(bench_ctx, rk, config4_full, mode):
+    """Every instance of the full config-4 batch: the batched result (one
+    persistent launch over the bucketed work queue, the bench's tuning
+    table) equals the oracle's, and so does each instance searched alone."""
+    insts, refs = config4_full
+    offs, o = [], 0
+    for s in insts:
+        offs.append(o)
+        o += (len(s.text) + 255) // 256 * 256
+    buf = torch.empty(o, dtype=torch.uint8, device="cuda:0")
+    for s, off in zip(insts, offs):
+        buf[off:off + len(s.text)].copy_(torch.from_numpy(s.text))
+    texts = [buf[off:off + len(s.text)] for s, off in zip(insts, offs)]
+    bp = rk.BatchPlan(bench_ctx, texts, [s.patterns for s in insts], mode)
+    off_b, pos_b = bp.search()
+    torch.cuda.synchronize()
+    per = bp.split(off_b, pos_b)
+    bp.close()
+    bad = [(i, j) for i, s in enumerate(insts) for j in range(len(s.patterns))
+           if per[i][j].astype(np.uint64).tolist() != refs[i][j].tolist()]
+    assert not bad, "batched != oracle at %s" % bad[:5]
+    for i, s in enumerate(insts):
+        plan = rk.Plan(bench_ctx, s.patterns, mode)
+        so, sp = plan.search(texts[i])
+        lists = oracle.split(so.cpu().numpy().astype(np.uint64), sp.cpu().numpy().astype(np.uint64))
+        plan.close()
+        for j in range(len(s.patterns)):
+            assert lists[j].tolist() == refs[i][j].tolist(), ("solo", i, j)
+    del buf

@@ -221,3 +221,56 @@ def test_dense_steps_size_their_slabs(ctx, rk, corpora):
         assert st["completed"] == len(reqs) and st["failed"] == 0
         assert st["steps"] >= len(reqs) // 3
         srv.close()
+
+
+def test_admission_wait_is_bounded(ctx, rk, corpora):
+    """A client that holds every result unreleased fills the arena: a later
+    step that finds no room while nothing else is in flight ends RK_ENOSPACE
+    after the admission timeout instead of waiting forever; the requests
+    admitted before it are exact, and releasing results lets new steps run."""
+    text = corpora[2]
+    h = text.cpu().numpy()
+    pats = [h[o:o + m].tobytes() for o, m in ((10, 1), (2000, 1), (40000, 2))]
+    ref = oracle.search(h, pats)
+    hits = int(ref[0][-1])
+    srv = rk.Server(ctx, arena_bytes=48 * hits, max_inflight=1, max_step_requests=1, admission_timeout_s=0.2)
+    srv.add_corpus(text)
+    t0 = time.perf_counter()
+    rids = [srv.submit(0, pats) for _ in range(4)]
+    res = [srv.wait(r, timeout=30.0, fetch=False) for r in rids]
+    assert time.perf_counter() - t0 < 20.0
+    status = [r["status"] for r in res]
+    assert status[0] == 0 and rk._lib.RK_ENOSPACE in status, status
+    assert set(status) <= {0, rk._lib.RK_ENOSPACE}, status
+    first = srv.wait(rids[0])
+    assert first["offsets"].tolist() == ref[0].tolist() and first["positions"].tolist() == ref[1].tolist()
+    for r in rids:
+        srv.release(r)
+    again = srv.wait(srv.submit(0, pats), timeout=30.0)
+    assert again["status"] == 0 and again["positions"].tolist() == ref[1].tolist()
+    srv.close()
+
+
+def test_request_timeout(ctx, rk, corpora):
+    """Requests that wait longer than the request timeout for a step end
+    RK_ETIMEDOUT; the others are exact."""
+    text = corpora[0]
+    h = text.cpu().numpy()
+    srv = rk.Server(ctx, max_inflight=1, max_step_requests=1, request_timeout_s=0.002)
+    srv.add_corpus(text)
+    reqs = [[h[o:o + 8].tobytes(), h[o + 50:o + 66].tobytes()] for o in range(0, 30000, 1000)]
+    rids = [srv.submit(0, r) for r in reqs]
+    srv.drain()
+    timed_out = 0
+    for r, rid in zip(reqs, rids):
+        res = srv.wait(rid, timeout=0.0)
+        if res["status"] == rk._lib.RK_ETIMEDOUT:
+            timed_out += 1
+            continue
+        assert res["status"] == 0
+        ro, rp = oracle.search(h, r)
+        assert res["offsets"].tolist() == ro.tolist() and res["positions"].tolist() == rp.tolist()
+        srv.release(rid)
+    assert timed_out >= 1
+    assert srv.stats()["failed"] >= timed_out
+    srv.close()

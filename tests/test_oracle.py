@@ -241,3 +241,17 @@ def test_config3_reduced_sampled_patterns_found():
     for j, o in enumerate(s.manifest["sampled_offsets"].tolist()):
         assert o in pos[int(off[j]):int(off[j + 1])].tolist()
     check_against_find(tb, s.patterns, off, pos)
+
+
+def test_search_long_patterns_against_find():
+    """Patterns of 65..1024 bytes (longer than any window the GPU scans roll)
+    against a bytes.find loop, with overlapping occurrences in a run."""
+    g = np.random.default_rng(77)
+    text = bytearray(np.frombuffer(g.bytes(20000), np.uint8) % 4 + 65)
+    text[5000:7000] = b"A" * 2000
+    text = bytes(text)
+    pats = [text[o:o + m] for o, m in ((100, 65), (3000, 200), (9000, 1024), (4950, 300))]
+    pats += [b"A" * 700, b"A" * 1024, bytes(g.integers(65, 69, size=500, dtype=np.uint8))]
+    off, pos = oracle.search(text, pats)
+    for j, p in enumerate(pats):
+        assert pos[off[j]:off[j + 1]].tolist() == find_all(text, p), j
