@@ -196,6 +196,33 @@ rk_status rk_scan_dump(rk_ctx *ctx, const uint8_t *text_dev, uint64_t n, uint32_
 rk_status rk_stream_read(rk_ctx *ctx, const void *data_dev, uint64_t n, uint32_t *out_dev, uint32_t grid,
                          rk_stream s);
 
+/* ------------------------------------------------ search without allocation */
+
+/* Largest scratch + work memory rk_search_static can use (bytes): the size of
+ * the library's static device array, of which each GPU holds one copy from
+ * load until the process ends. */
+#define RK_STATIC_SCRATCH_BYTES (64ull << 20)
+
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): rk_count followed by
+ * rk_collect with their scratch and work memory taken from the library's
+ * static device array instead of caller buffers.  No hipMalloc, hipFree or
+ * other allocation happens in the call.  The caller passes the text and the
+ * outputs (offsets_dev: k + 1 entries, positions_dev: capacity entries, as for
+ * rk_collect); *total_host receives the number of hits.  Returns RK_ENOSPACE
+ * (with the reason in rk_ctx_last_error) when the count's scratch or the
+ * collect's work memory would exceed RK_STATIC_SCRATCH_BYTES, or when
+ * capacity is below the total (then *total_host is set and nothing is
+ * written).  Synchronises s once (after the count).  Every call on one GPU
+ * shares that GPU's array and leaves its contents behind: calls that overlap
+ * on one GPU (other streams or host threads) race and must be serialised by
+ * the caller. */
+rk_status rk_search_static(rk_ctx *ctx, const rk_plan *plan, const uint8_t *text_dev, uint64_t n,
+                           uint64_t *offsets_dev, uint64_t *positions_dev, uint64_t capacity,
+                           uint64_t *total_host, rk_stream s);
+/* RK_STATIC_SCRATCH_BYTES as built into the library. */
+uint64_t rk_static_scratch_bytes(void);
+
 /* ------------------------------------------- texts in host memory or a file */
 
 /* Result of a streamed search, in host memory owned by the library: pattern

@@ -129,6 +129,9 @@ SIGNATURES = {
     "rk_paper_positions": (ctypes.c_int, [c_void, c_void, ctypes.c_uint64, c_void, ctypes.c_uint64, c_void,
                                           ctypes.c_uint64, c_u64p, c_void]),
     "rk_stream_read": (ctypes.c_int, [c_void, c_void, ctypes.c_uint64, c_void, ctypes.c_uint32, c_void]),
+    "rk_search_static": (ctypes.c_int, [c_void, c_void, c_void, ctypes.c_uint64, c_void, c_void, ctypes.c_uint64,
+                                        c_u64p, c_void]),
+    "rk_static_scratch_bytes": (ctypes.c_uint64, []),
     "rk_autotune": (ctypes.c_int, [c_void, ctypes.c_uint64, c_u32p, ctypes.c_uint32, ctypes.c_char_p]),
     "rk_autotune_load": (ctypes.c_int, [c_void, ctypes.c_char_p]),
     "rk_autotune_choice": (ctypes.c_int, [c_void, ctypes.c_int, ctypes.c_uint32]),

@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librk.so")
 SOURCES = (["rk_%s_exact_%s.hip" % (k, g) for g in ("256x132", "512x68", "256x68", "256x36") for k in ("scan", "list")] +
-           ["rk_scan_screen.hip", "rk_device.hip", "rk_paper.hip", "rk_host.cpp", "rk_exec.cpp", "rk_tune.cpp",
+           ["rk_scan_screen.hip", "rk_device.hip", "rk_paper.hip", "rk_noalloc.hip", "rk_host.cpp", "rk_exec.cpp", "rk_tune.cpp",
             "rk_stream.cpp", "rk_server.cpp"])
 ARCH = os.environ.get("RK_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", "-Wno-unused-value", "-Wno-unused-result",

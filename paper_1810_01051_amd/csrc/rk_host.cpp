@@ -492,6 +492,11 @@ rk_status rk_ctx_create(int device, uint64_t d, uint64_t q, rk_ctx **out) {
   for (int md = 0; md < 3; ++md)
     for (int m = 0; m <= RK_MAX_M; ++m) c->tune[md][m] = -1;
   prepare_scan_kernels();
+  if (static_scratch_setup(c) != RK_OK) {
+    hipHostFree(c->pinned);
+    delete c;
+    return RK_EDEVICE;
+  }
   *out = c;
   return RK_OK;
 }

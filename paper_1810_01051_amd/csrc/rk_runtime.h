@@ -63,6 +63,7 @@ struct rk_ctx {
   rk::CountMemo memo[16];
   uint32_t memo_next = 0;
   void *dump_dev = nullptr;    // device copy of the dump image
+  void *static_scratch = nullptr;  // this device's copy of the static scratch array (rk_search_static)
 };
 
 struct rk_plan {
@@ -167,5 +168,6 @@ hipError_t launch_window_hashes(const uint8_t *text, uint64_t n, uint32_t m, con
 hipError_t launch_fill_u32(uint32_t *p, uint64_t words, uint32_t v, hipStream_t s);
 rk_status tune_run(rk_ctx *ctx, uint64_t n, const uint32_t *lengths, uint32_t nl, const char *path);
 rk_status tune_load(rk_ctx *ctx, const char *path);
+rk_status static_scratch_setup(rk_ctx *ctx);
 
 }  // namespace rk
