@@ -280,6 +280,11 @@ def bench_config3(args):
     t0 = time.perf_counter()
     s = rkgen.config3()
     log("config3 generated in %.1fs" % (time.perf_counter() - t0))
+    if args.patterns3 != "all":
+        # the cost split: the sampled half (hits every ~32 bytes) or the
+        # random half (almost no hits) alone
+        half = len(s.patterns) // 2
+        s.patterns = s.patterns[:half] if args.patterns3 == "sampled" else s.patterns[half:]
     text = torch.from_numpy(s.text).to("cuda:0")
     ctx = make_ctx(rk, args)
     n = text.numel()
@@ -319,7 +324,8 @@ def bench_config3(args):
         "value": out["screen"]["GB/s"], "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": out["screen"]["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
-        "config": {"workload": "multi-pattern: %d B Zipf(1.1) word text, 1024 patterns m=16 (512 sampled)" % n,
+        "config": {"workload": "multi-pattern: %d B Zipf(1.1) word text, %d patterns m=16 (%s of 512 sampled + "
+                               "512 random)" % (n, len(s.patterns), args.patterns3),
                    "results": out, "oracle_prefix_64MiB_ok": ok},
         "cpu_baseline": cpu,
     }
@@ -557,6 +563,13 @@ def bench_config5(args):
                                            max_inflight=args.inflight, max_step_patterns=args.step_patterns,
                                            use_graphs=True)
         log("config5 batched %d: %s" % (rate, results["batched_%d" % rate]))
+    # graphs off with everything else held (merging, steps in flight): what
+    # launching each step's passes as graphs is worth
+    for rate in ([] if args.no_graph_ab else args.rates):
+        results["batched_no_graphs_%d" % rate] = run(rate, args.warm5, args.duration5, arena_bytes=args.arena,
+                                                     max_inflight=args.inflight,
+                                                     max_step_patterns=args.step_patterns, use_graphs=False)
+        log("config5 batched, no graphs %d: %s" % (rate, results["batched_no_graphs_%d" % rate]))
     # the baseline: one request per step, one step at a time, plain launches,
     # on the same request stream at every offered rate
     for rate in ([] if args.no_unbatched else args.rates):
@@ -686,6 +699,8 @@ def main():
                          "paper: the paper's Tables 1-3 in paper mode")
     ap.add_argument("--paper-n", type=int, default=320 * 10 ** 6, help="paper workload text bytes")
     ap.add_argument("--count4", type=int, default=4096, help="config4 instances")
+    ap.add_argument("--patterns3", default="all", choices=["all", "sampled", "random"],
+                    help="config3: every pattern, or only the sampled / only the random half")
     ap.add_argument("--corpora", type=int, default=64, help="config5 corpora")
     ap.add_argument("--corpus-bytes", type=int, default=1 << 30, help="config5 bytes per corpus")
     ap.add_argument("--rates", type=float, nargs="+", default=[500, 2000, 8000], help="config5 offered req/s")
@@ -696,6 +711,7 @@ def main():
     ap.add_argument("--step-patterns", type=int, default=None,
                     help="config5 merged patterns per step (default: the library's)")
     ap.add_argument("--no-unbatched", action="store_true", help="config5: skip the one-request-per-launch runs")
+    ap.add_argument("--no-graph-ab", action="store_true", help="config5: skip the graphs-off runs")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (for PMC byte-counter calibration)")
     args = ap.parse_args()

@@ -65,14 +65,19 @@ typedef enum {
 /* Scan modes.  Both give identical results.
  *   RK_MODE_EXACT : every window's d=256 / q=2^61-1 hash is rolled and tested
  *                   against the pattern-hash set; equal hashes are byte-checked.
- *   RK_MODE_SCREEN: every window gets the paper's shift-and-add hash
+ *   RK_MODE_SCREEN: every window gets a shift-and-add hash in the paper's form
  *                   h <- (h << s) + c taken mod 2^32 (the polynomial hash
- *                   with d = 2^s, q = 2^32; shift s in {1,2,4,8} chosen per
- *                   pattern length so that s*m >= 32, s = 1 being the paper's
- *                   form), tested against the set of the patterns' shift-add
+ *                   with d = 2^s, q = 2^32) with s = 8 for patterns shorter
+ *                   than 8 bytes (masked to the window below 4), 4 for 8..15
+ *                   and 2 from 16 (so the hash covers the last 32/s bytes of
+ *                   a window: every pattern of 16 bytes or more shares one
+ *                   stream), tested against the set of the patterns' shift-add
  *                   hashes; windows in the set are byte-checked against the
- *                   patterns with that hash.  A true occurrence always passes
- *                   the test, so no occurrence is lost.
+ *                   patterns with that hash (the byte check stands in for the
+ *                   exact hash, which can only pass what the bytes pass).  A
+ *                   true occurrence always passes the test, so no occurrence
+ *                   is lost.  The paper's own s = 1 over whole windows is
+ *                   rk_paper_search.
  *   RK_MODE_AUTO  : RK_MODE_SCREEN. */
 typedef enum { RK_MODE_AUTO = 0, RK_MODE_EXACT = 1, RK_MODE_SCREEN = 2 } rk_mode;
 
@@ -305,17 +310,33 @@ uint64_t rk_plan_text_bytes(const rk_plan *plan);
 
 /* ---------------------------------------------------------------- autotuner */
 
-/* Times every scan geometry of the built-in table on a synthetic text of n
- * bytes for pattern length m (both modes), verifies each candidate's hits
- * against the first, and stores the fastest per (mode, length class) in the
- * context.  If path is non-NULL the table is also written there as JSON.
- * Synchronises the device. */
+/* Times every scan geometry of the built-in table on a synthetic DNA text of
+ * n bytes (n >= 64 KiB; byte i = "ACGT"[x_i >> 62] for Knuth's MMIX linear
+ * congruential sequence x_{i+1} = 6364136223846793005 x_i + 1442695040888963407,
+ * x_0 = 0x181001051):
+ *   - for one pattern of each length in lengths (the text's bytes at n/3),
+ *     both modes, the single-bucket kernel of one-pattern searches;
+ *   - for each batch bucket (m-class 0..4: lengths 1-3, 4-7, 8-15, 16-31,
+ *     32-64; k-class 0..3: 1, 4, 32, 256 patterns), both modes, the general
+ *     kernel over a one-instance batch plan of the text's first n_b bytes
+ *     (n_b = min(n, 1 MiB) for m-class 0, min(n, 32 MiB) otherwise), pattern j
+ *     of length lo + j mod (hi - lo + 1) copied from the text at
+ *     (n_b/3 + 7919 j) mod (n_b - m + 1), reversed when j is odd,
+ * stores the fastest geometry of each in the context (batch plans take each
+ * m-bucket image's geometry from the bucket table) and, if path is non-NULL,
+ * writes the table as JSON with every candidate's time, hit count and digest
+ * of its result (sum of v[i] * (2i + 1) mod 2^64 over the offsets followed by
+ * the positions).  Every candidate must return the same hits (RK_EDEVICE otherwise).
+ * Synchronises the device.  (The paper's Tables 1-2 vary threads per block
+ * for the same reason: the launch shape decides the speed.) */
 rk_status rk_autotune(rk_ctx *ctx, uint64_t n, const uint32_t *lengths, uint32_t nlengths,
                       const char *path);
 /* Load a table written by rk_autotune (entries for another gfx arch are ignored). */
 rk_status rk_autotune_load(rk_ctx *ctx, const char *path);
-/* Geometry index the scan uses for (mode, pattern length m). */
+/* Geometry index the scan uses for (mode, pattern length m) of one-pattern searches. */
 int rk_autotune_choice(const rk_ctx *ctx, int mode, uint32_t m);
+/* Geometry index of a batch bucket (mode, m-class, k-class); -1 if not tuned. */
+int rk_autotune_bucket_choice(const rk_ctx *ctx, int mode, int mclass, int kclass);
 
 #ifdef __cplusplus
 }

@@ -135,6 +135,7 @@ SIGNATURES = {
     "rk_autotune": (ctypes.c_int, [c_void, ctypes.c_uint64, c_u32p, ctypes.c_uint32, ctypes.c_char_p]),
     "rk_autotune_load": (ctypes.c_int, [c_void, ctypes.c_char_p]),
     "rk_autotune_choice": (ctypes.c_int, [c_void, ctypes.c_int, ctypes.c_uint32]),
+    "rk_autotune_bucket_choice": (ctypes.c_int, [c_void, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
 }
 
 _lib = None

@@ -16,7 +16,7 @@ namespace rk {
 
 // images are built per real instance (defined in rk_host.cpp)
 rk_status build_instance_images(rk_ctx *ctx, const uint8_t *bytes, const uint64_t *offs, uint32_t k,
-                                uint32_t pid_base, int mode, uint32_t src, std::vector<VInst> &vinsts,
+                                uint32_t pid_base, int mode, uint32_t src, bool by_class, std::vector<VInst> &vinsts,
                                 std::vector<uint8_t> &blob);
 
 static inline uint64_t align_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
@@ -26,6 +26,23 @@ static int pick_cfg(const rk_ctx *ctx, int mode, uint32_t m) {
   const int md = mode == RK_MODE_EXACT ? 1 : 2;
   if (m >= 1 && m <= RK_MAX_M && ctx->tune[md][m] >= 0) return ctx->tune[md][m];
   return 0;
+}
+
+// Geometry of one m-bucket image of a batch: the tuned choice for its
+// (mode, m-class, pattern-count class), else the single-pattern choice for
+// its longest stream.
+static int pick_bucket_cfg(const rk_ctx *ctx, int mode, const VInst &v) {
+  if (ctx->tile_cfg >= 0) return ctx->tile_cfg;
+  const int md = mode == RK_MODE_EXACT ? 1 : 2;
+  if (v.mclass >= 0 && ctx->tune_b[md][v.mclass][k_class(v.npat)] >= 0) return ctx->tune_b[md][v.mclass][k_class(v.npat)];
+  return pick_cfg(ctx, mode, std::min(v.max_m, kStreamM));
+}
+
+static int part_family(int mode, const std::vector<VInst> &vs, const std::vector<uint32_t> &members) {
+  if (mode == RK_MODE_EXACT) return kFamExact;
+  for (uint32_t i : members)
+    if (!vs[i].only_one_list) return kFamScreen;
+  return kFamScreen1;
 }
 
 // Host half of a plan: images, and for batches the instance descriptors and
@@ -58,7 +75,7 @@ rk_status plan_build_host(rk_ctx *ctx, const rk_instance *inst, uint32_t count, 
     R.pid_base = (uint32_t)ktot;
     R.k = I.k;
     P->insts.push_back(R);
-    rk_status st = build_instance_images(ctx, I.bytes_host, I.offsets_host, I.k, (uint32_t)ktot, mode, i,
+    rk_status st = build_instance_images(ctx, I.bytes_host, I.offsets_host, I.k, (uint32_t)ktot, mode, i, batch,
                                          P->vinsts, blob);
     if (st != RK_OK) return st;
     for (uint32_t j = 0; j < I.k; ++j) {
@@ -82,6 +99,7 @@ rk_status plan_build_host(rk_ctx *ctx, const rk_instance *inst, uint32_t count, 
   for (const VInst &v : P->vinsts)
     if (mode != RK_MODE_EXACT && !v.only_one_list) P->fam = kFamScreen;
   for (const VInst &v : P->vinsts) P->img_cap = std::max(P->img_cap, v.lds_bytes);
+  P->img_cap = (uint32_t)align_up(P->img_cap, 16);
   if (!batch && P->vinsts.size() == 1 && P->vinsts[0].nbuckets == 1) {
     memcpy(&P->list_desc, blob.data() + P->vinsts[0].img_off + sizeof(ImageHeader), sizeof(BucketDesc));
     P->list1 = P->list_desc.kind == kListScreen || P->list_desc.kind == kListExact;
@@ -100,11 +118,42 @@ rk_status plan_build_host(rk_ctx *ctx, const rk_instance *inst, uint32_t count, 
       P->list_rec1 = used == 1 ? rec : 0;
     }
   }
-  P->img_cap = (uint32_t)align_up(P->img_cap, 16);
-  if (batch) {
-    const uint32_t W = kTileCfgs[P->cfg].wg * kTileCfgs[P->cfg].c;
-    uint64_t base = 0;
-    for (const VInst &v : P->vinsts) {
+  if (!batch) {
+    // one text: one part, its tiles counted per search (they depend on n)
+    Part pt;
+    pt.cfg = P->cfg;
+    pt.fam = P->fam;
+    pt.img_cap = P->img_cap;
+    pt.ninst = (uint32_t)P->vinsts.size();
+    P->parts.assign(1, pt);
+    return RK_OK;
+  }
+  // Batch: every (instance, m-bucket) image gets the geometry tuned for its
+  // bucket; the images of one geometry form a part, scanned by one
+  // persistent launch over a work queue of (instance, m-bucket, tile) items
+  // ordered by m-bucket (then heavier images first, then instance), so that a
+  // workgroup keeps one image across consecutive pops.
+  std::vector<uint32_t> members[kMaxParts];
+  for (uint32_t vi = 0; vi < P->vinsts.size(); ++vi) {
+    VInst &v = P->vinsts[vi];
+    v.cfg = pick_bucket_cfg(ctx, mode, v);
+    members[v.cfg].push_back(vi);
+  }
+  uint64_t base = 0;
+  for (int c = 0; c < kNumTileCfg; ++c) {
+    if (members[c].empty()) continue;
+    Part pt;
+    pt.cfg = c;
+    pt.fam = part_family(mode, P->vinsts, members[c]);
+    for (uint32_t vi : members[c]) pt.img_cap = std::max(pt.img_cap, P->vinsts[vi].lds_bytes);
+    pt.img_cap = (uint32_t)align_up(pt.img_cap, 16);
+    pt.inst0 = (uint32_t)descs.size();
+    pt.ninst = (uint32_t)members[c].size();
+    pt.tile0 = base;
+    const uint32_t W = kTileCfgs[c].wg * kTileCfgs[c].c;
+    std::vector<uint64_t> first(members[c].size());
+    for (size_t q = 0; q < members[c].size(); ++q) {
+      const VInst &v = P->vinsts[members[c][q]];
       const RealInst &R = P->insts[v.src];
       InstDesc d;
       memset(&d, 0, sizeof d);
@@ -114,22 +163,30 @@ rk_status plan_build_host(rk_ctx *ctx, const rk_instance *inst, uint32_t count, 
       d.ntiles = (R.n + W - 1) / W;
       d.img_off = v.img_off;
       d.lds_bytes = v.lds_bytes;
+      first[q] = base;
       descs.push_back(d);
       base += d.ntiles;
     }
-    P->total_tiles = base;
-    // queue order: heavier tiles (more groups, longer patterns) first, then by
-    // instance, so a workgroup keeps one instance image across consecutive pops
-    std::vector<uint32_t> order(P->vinsts.size());
-    for (uint32_t i = 0; i < order.size(); ++i) order[i] = i;
+    pt.ntiles = base - pt.tile0;
+    std::vector<uint32_t> order(members[c].size());
+    for (uint32_t q = 0; q < order.size(); ++q) order[q] = q;
     std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
-      const VInst &x = P->vinsts[a], &y = P->vinsts[b];
+      const VInst &x = P->vinsts[members[c][a]], &y = P->vinsts[members[c][b]];
+      if (x.mclass != y.mclass) return x.mclass < y.mclass;
       if (x.nbuckets != y.nbuckets) return x.nbuckets > y.nbuckets;
       return x.max_m > y.max_m;
     });
-    for (uint32_t vi : order)
-      for (uint64_t t = 0; t < descs[vi].ntiles; ++t) items.push_back(descs[vi].tile_base + t);
-    P->nitems = items.size();
+    pt.item0 = items.size();
+    for (uint32_t q : order)
+      for (uint64_t t = 0; t < descs[pt.inst0 + q].ntiles; ++t) items.push_back(first[q] + t);
+    pt.nitems = items.size() - pt.item0;
+    P->parts.push_back(pt);
+  }
+  P->total_tiles = base;
+  P->nitems = items.size();
+  if (!P->parts.empty()) {
+    P->cfg = P->parts[0].cfg;
+    P->fam = P->parts[0].fam;
   }
   return RK_OK;
 }
@@ -182,18 +239,29 @@ rk_status plan_build(rk_ctx *ctx, const rk_instance *inst, uint32_t count, int m
 
 rk_status make_layout(rk_ctx *ctx, const rk_plan *plan, uint64_t n, Layout &L) {
   L = Layout();
-  L.W = kTileCfgs[plan->cfg].wg * kTileCfgs[plan->cfg].c;
-  if (plan->batch) {
-    L.T = plan->total_tiles;
-  } else {
-    if (n > RK_MAX_N) return set_err(ctx, RK_EUNSUPPORTED, "text longer than 2^40-1 bytes");
-    L.T1 = (n + L.W - 1) / L.W;
-    L.T = L.T1 * plan->vinsts.size();
-  }
   // staging records per tile: one per 64 text bytes for a single pattern
   // (hits are rare), one per 16 for pattern sets (sampled patterns hit often);
   // a tile with more hits is rescanned by the collect pass
-  L.S = ctx->slab_cap ? ctx->slab_cap : (plan->k_total > 1 ? L.W / 16 : L.W / 64);
+  auto slots = [&](uint32_t W) { return ctx->slab_cap ? ctx->slab_cap : (plan->k_total > 1 ? W / 16 : W / 64); };
+  if (plan->batch) {
+    for (const Part &pt : plan->parts) {
+      PartRun r;
+      r.tile0 = pt.tile0;
+      r.ntiles = pt.ntiles;
+      r.W = kTileCfgs[pt.cfg].wg * kTileCfgs[pt.cfg].c;
+      r.S = slots(r.W);
+      L.parts.push_back(r);
+    }
+    L.T = plan->total_tiles;
+  } else {
+    if (n > RK_MAX_N) return set_err(ctx, RK_EUNSUPPORTED, "text longer than 2^40-1 bytes");
+    PartRun r;
+    r.W = kTileCfgs[plan->cfg].wg * kTileCfgs[plan->cfg].c;
+    L.T1 = (n + r.W - 1) / r.W;
+    r.ntiles = L.T = L.T1 * plan->vinsts.size();
+    r.S = slots(r.W);
+    L.parts.push_back(r);
+  }
   uint64_t o = 0;
   auto take = [&o](uint64_t bytes) {
     const uint64_t r = o;
@@ -206,7 +274,7 @@ rk_status make_layout(rk_ctx *ctx, const rk_plan *plan, uint64_t n, Layout &L) {
   L.offsets = take(L.T * 8);
   L.ovf = take(L.T * 8);
   L.tmp = take(scan_tmp_words(L.T) * 8);
-  L.slabs = take(L.T * (uint64_t)L.S * 8);
+  for (PartRun &r : L.parts) r.slabs = take(r.ntiles * (uint64_t)r.S * 8);
   L.total = o;
   return RK_OK;
 }
@@ -280,23 +348,21 @@ static uint32_t scan_grid(rk_ctx *ctx, int cfg, int fam, uint32_t lds, uint64_t 
   return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(g, nitems));
 }
 
-// Fills ScanParams common to the count pass and the rescan.
-static void base_params(const rk_plan *plan, const Layout &L, uint8_t *sc, ScanParams &p) {
+// Fills ScanParams common to the count pass and the rescan of part pi.
+static void base_params(const rk_plan *plan, const Layout &L, uint32_t pi, uint8_t *sc, ScanParams &p) {
   memset(&p, 0, sizeof p);
-  if (plan->batch) {
-    p.inst = plan->inst_dev;
-    p.ninst = (uint32_t)plan->vinsts.size();
-  } else {
-    p.inst = (const InstDesc *)(sc + L.inst);
-    p.ninst = (uint32_t)plan->vinsts.size();
-  }
-  p.img_cap = plan->img_cap;
+  const Part &pt = plan->parts[pi];
+  const PartRun &r = L.parts[pi];
+  p.inst = plan->batch ? plan->inst_dev + pt.inst0 : (const InstDesc *)(sc + L.inst);
+  p.ninst = pt.ninst;
+  p.img_cap = pt.img_cap;
   p.blob = plan->blob_dev;
   p.tile_counts = (uint32_t *)(sc + L.counts);
-  p.slab_cap = L.S;
+  p.slab_cap = r.S;
+  p.tile0 = r.tile0;
   p.total = (unsigned long long *)(sc + L.ctr);
-  p.ovf_count = (uint32_t *)(sc + L.ctr + 8);
-  p.ovf_list = (uint64_t *)(sc + L.ovf);
+  p.ovf_count = (uint32_t *)(sc + L.ctr + kCtrOvf) + pi;
+  p.ovf_list = (uint64_t *)(sc + L.ovf) + r.tile0;  // the part's own overflow list
   p.grab = 1;
 }
 
@@ -342,21 +408,11 @@ rk_status count_enqueue(rk_ctx *ctx, const rk_plan *plan, const uint8_t *text, u
     if (e != hipSuccess) return hip_err(ctx, e, "per-pattern count reset");
   }
   if (L.T == 0) return RK_OK;
-  ScanParams p;
-  base_params(plan, L, sc, p);
-  p.items = plan->batch ? plan->items_dev : nullptr;
-  p.nitems = plan->batch ? plan->nitems : L.T;
-  p.out = (uint64_t *)(sc + L.slabs);
-  p.pid_counts = (unsigned long long *)counts;
   const bool use_queue = ctx->queue == 1 || (ctx->queue == -1 && plan->batch);
-  if (use_queue) {
-    p.queue = (uint32_t *)(sc + L.ctr + 12);
-    p.grab = 1;
-  }
-  const uint32_t lds = scan_lds_bytes(plan->cfg, plan->img_cap);
   int slot;
   if (plan->list1 && !use_queue) {
     // one text, one bucket with register targets: the single-bucket kernel
+    const PartRun &r = L.parts[0];
     ListParams lp;
     memset(&lp, 0, sizeof lp);
     lp.text = text;
@@ -365,14 +421,14 @@ rk_status count_enqueue(rk_ctx *ctx, const rk_plan *plan, const uint8_t *text, u
     lp.gimg = plan->blob_dev + plan->vinsts[0].img_off;
     lp.D = plan->list_desc;
     lp.rot = (8u * plan->list_desc.m) % 61u;
-    lp.slab_cap = L.S;
+    lp.slab_cap = r.S;
     lp.rec1 = plan->list_rec1;
-    lp.tile_counts = p.tile_counts;
-    lp.out = p.out;
-    lp.total = p.total;
-    lp.ovf_count = p.ovf_count;
-    lp.ovf_list = p.ovf_list;
-    lp.pid_counts = p.pid_counts;
+    lp.tile_counts = (uint32_t *)(sc + L.counts);
+    lp.out = (uint64_t *)(sc + r.slabs);
+    lp.total = (unsigned long long *)(sc + L.ctr);
+    lp.ovf_count = (uint32_t *)(sc + L.ctr + kCtrOvf);
+    lp.ovf_list = (uint64_t *)(sc + L.ovf);
+    lp.pid_counts = (unsigned long long *)counts;
     uint32_t grid = ctx->grid;
     if (!grid) {
       int blocks = 0;
@@ -387,13 +443,27 @@ rk_status count_enqueue(rk_ctx *ctx, const rk_plan *plan, const uint8_t *text, u
     e = prof_end(ctx, s, slot);
     if (e != hipSuccess) return hip_err(ctx, e, "profiling event");
   } else {
-  const uint32_t grid = scan_grid(ctx, plan->cfg, plan->fam, lds, p.nitems);
-  e = prof_begin(ctx, s, 0, &slot);
-  if (e != hipSuccess) return hip_err(ctx, e, "profiling event");
-  e = launch_scan(plan->cfg, plan->fam, p, grid, lds, s);
-  if (e != hipSuccess) return hip_err(ctx, e, "scan launch");
-  e = prof_end(ctx, s, slot);
-  if (e != hipSuccess) return hip_err(ctx, e, "profiling event");
+    // one persistent launch per part (batches: per scan geometry)
+    for (uint32_t pi = 0; pi < plan->parts.size(); ++pi) {
+      const Part &pt = plan->parts[pi];
+      const PartRun &r = L.parts[pi];
+      if (r.ntiles == 0) continue;
+      ScanParams p;
+      base_params(plan, L, pi, sc, p);
+      p.items = plan->batch ? plan->items_dev + pt.item0 : nullptr;
+      p.nitems = plan->batch ? pt.nitems : r.ntiles;
+      p.out = (uint64_t *)(sc + r.slabs);
+      p.pid_counts = (unsigned long long *)counts;
+      if (use_queue) p.queue = (uint32_t *)(sc + L.ctr + kCtrQueue) + pi;
+      const uint32_t lds = scan_lds_bytes(pt.cfg, pt.img_cap);
+      const uint32_t grid = scan_grid(ctx, pt.cfg, pt.fam, lds, p.nitems);
+      e = prof_begin(ctx, s, 0, &slot);
+      if (e != hipSuccess) return hip_err(ctx, e, "profiling event");
+      e = launch_scan(pt.cfg, pt.fam, p, grid, lds, s);
+      if (e != hipSuccess) return hip_err(ctx, e, "scan launch");
+      e = prof_end(ctx, s, slot);
+      if (e != hipSuccess) return hip_err(ctx, e, "profiling event");
+    }
   }
   CountMemo &mm = ctx->memo[ctx->memo_next++ % 16];
   mm.scratch = scratch;
@@ -405,12 +475,12 @@ rk_status count_enqueue(rk_ctx *ctx, const rk_plan *plan, const uint8_t *text, u
 }
 
 rk_status count_finish(rk_ctx *ctx, const rk_plan *plan, void *scratch, hipStream_t s, uint64_t *total) {
-  hipError_t e = hipMemcpyAsync(ctx->pinned, scratch, 16, hipMemcpyDeviceToHost, s);
+  hipError_t e = hipMemcpyAsync(ctx->pinned, scratch, 64, hipMemcpyDeviceToHost, s);
   if (e != hipSuccess) return hip_err(ctx, e, "total readback");
   e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_err(ctx, e, "scan");
   *total = ctx->pinned[0];
-  const uint32_t ovf = (uint32_t)(ctx->pinned[1] & 0xFFFFFFFFu);
+  const uint32_t ovf = ovf_total(ctx->pinned);
   for (auto &mm : ctx->memo)
     if (mm.scratch == scratch && mm.plan == plan) {
       mm.total = *total;
@@ -485,30 +555,38 @@ rk_status collect_enqueue_known(rk_ctx *ctx, const rk_plan *plan, uint64_t n, vo
   if (e != hipSuccess) return hip_err(ctx, e, "tile scan");
   WorkLayout WL = work_layout(total);
   uint64_t *target = k == 1 ? positions : (uint64_t *)((uint8_t *)work + WL.a);
-  e = launch_compact((const uint32_t *)(sc + L.counts), tile_off, L.T, (const uint64_t *)(sc + L.slabs), L.S, target,
-                     s);
-  if (e != hipSuccess) return hip_err(ctx, e, "compact");
+  for (const PartRun &r : L.parts) {
+    e = launch_compact((const uint32_t *)(sc + L.counts) + r.tile0, tile_off + r.tile0, r.ntiles,
+                       (const uint64_t *)(sc + r.slabs), r.S, target, s);
+    if (e != hipSuccess) return hip_err(ctx, e, "compact");
+  }
   e = prof_end(ctx, s, slot);
   if (e != hipSuccess) return hip_err(ctx, e, "profiling event");
-  // rescan of tiles whose hits did not fit their slab (count read on the device;
-  // skipped when the count pass reported none)
+  // rescan of tiles whose hits did not fit their slab, part by part (each
+  // part's count read on the device; skipped when the count pass reported none)
   if (overflow != 0) {
-    ScanParams p;
-    base_params(plan, L, sc, p);
-    p.items = (const uint64_t *)(sc + L.ovf);
-    p.nitems = L.T;
-    p.nitems_dev = (const uint32_t *)(sc + L.ctr + 8);
-    p.out = target;
-    p.tile_offsets = tile_off;
-    p.direct = 1;
-    const uint32_t lds = scan_lds_bytes(plan->cfg, plan->img_cap);
-    const uint32_t grid = std::min<uint32_t>(scan_grid(ctx, plan->cfg, plan->fam, lds, L.T), (uint32_t)ctx->num_cu);
-    e = prof_begin(ctx, s, 1, &slot);
-    if (e != hipSuccess) return hip_err(ctx, e, "profiling event");
-    e = launch_scan(plan->cfg, plan->fam, p, grid, lds, s);
-    if (e != hipSuccess) return hip_err(ctx, e, "rescan launch");
-    e = prof_end(ctx, s, slot);
-    if (e != hipSuccess) return hip_err(ctx, e, "profiling event");
+    for (uint32_t pi = 0; pi < plan->parts.size(); ++pi) {
+      const Part &pt = plan->parts[pi];
+      const PartRun &r = L.parts[pi];
+      if (r.ntiles == 0) continue;
+      ScanParams p;
+      base_params(plan, L, pi, sc, p);
+      p.items = p.ovf_list;
+      p.nitems = r.ntiles;
+      p.nitems_dev = p.ovf_count;
+      p.out = target;
+      p.tile_offsets = tile_off;
+      p.direct = 1;
+      const uint32_t lds = scan_lds_bytes(pt.cfg, pt.img_cap);
+      const uint32_t grid =
+          std::min<uint32_t>(scan_grid(ctx, pt.cfg, pt.fam, lds, r.ntiles), (uint32_t)ctx->num_cu);
+      e = prof_begin(ctx, s, 1, &slot);
+      if (e != hipSuccess) return hip_err(ctx, e, "profiling event");
+      e = launch_scan(pt.cfg, pt.fam, p, grid, lds, s);
+      if (e != hipSuccess) return hip_err(ctx, e, "rescan launch");
+      e = prof_end(ctx, s, slot);
+      if (e != hipSuccess) return hip_err(ctx, e, "profiling event");
+    }
   }
   e = prof_begin(ctx, s, 2, &slot);
   if (e != hipSuccess) return hip_err(ctx, e, "profiling event");

@@ -134,6 +134,7 @@ struct ScanParams {
   uint64_t dump_stride;
   uint64_t dump_cap;
   unsigned long long *pid_counts; // count mode, optional: hits per global pattern id
+  uint64_t tile0;             // count mode: global id of the first tile of out's slabs
 };
 
 // Kernel parameters of the single-bucket scan (one text, one bucket whose set

@@ -26,6 +26,16 @@ struct CountMemo {
   uint32_t overflow = 0xFFFFFFFFu;  // tiles whose hits did not fit their slab (unknown: all ones)
 };
 
+// Pattern-length class of a group (the m-bucket of batch work queues), by
+// the length its stream hashes: 0: 1-3, 1: 4-7, 2: 8-15, 3: 16-31, 4: 32-64.
+constexpr int kNumMClass = 5;
+inline int m_class(uint32_t m) { return m < 4 ? 0 : m < 8 ? 1 : m < 16 ? 2 : m < 32 ? 3 : 4; }
+// Pattern-count class of an image: 0: one pattern, 1: 2-4 (register
+// targets), 2: 5-64, 3: more.
+constexpr int kNumKClass = 4;
+inline int k_class(uint32_t k) { return k <= 1 ? 0 : k <= 4 ? 1 : k <= 64 ? 2 : 3; }
+constexpr int kMaxParts = kNumTileCfg;  // one persistent launch per scan geometry
+
 struct VInst {
   uint32_t src;       // real instance index
   uint32_t img_off;   // in the plan blob
@@ -33,7 +43,21 @@ struct VInst {
   uint32_t lds_bytes;  // leading bytes staged in LDS
   uint32_t nbuckets = 0;
   uint32_t max_m = 0;
+  uint32_t npat = 0;   // patterns in the image
+  int mclass = -1;     // m-bucket of its groups (batch plans), -1: mixed
+  int cfg = 0;         // scan geometry
   bool only_one_list = true;  // every bucket is a list screen with one target
+};
+
+// The virtual instances of a plan that share one scan geometry, scanned by
+// one persistent launch (a single-text plan has one part).
+struct Part {
+  int cfg = 0;
+  int fam = kFamScreen1;
+  uint32_t img_cap = 0;            // LDS bytes reserved for an image
+  uint32_t inst0 = 0, ninst = 0;   // its instance descriptors (batch: in inst_dev)
+  uint64_t item0 = 0, nitems = 0;  // its work-queue entries in items_dev (batch)
+  uint64_t tile0 = 0, ntiles = 0;  // its tiles in the plan's tile numbering (batch)
 };
 
 struct RealInst {
@@ -60,6 +84,7 @@ struct rk_ctx {
   std::vector<rk::ProfEvent> prof_events, free_events;
   int tune[3][RK_MAX_M + 1];
   uint8_t tune_measured[3][RK_MAX_M + 1] = {};
+  int tune_b[3][rk::kNumMClass][rk::kNumKClass];  // batch buckets: geometry per (mode, m-class, k-class)
   rk::CountMemo memo[16];
   uint32_t memo_next = 0;
   void *dump_dev = nullptr;    // device copy of the dump image
@@ -84,20 +109,40 @@ struct rk_plan {
   void *dev = nullptr;        // one device allocation: blob | instance descs | items
   uint8_t *blob_dev = nullptr;
   rk::InstDesc *inst_dev = nullptr;  // batch: fixed descriptors (sorted by tile_base)
-  uint64_t *items_dev = nullptr;     // batch: queue order of global tile ids
+  uint64_t *items_dev = nullptr;     // batch: queue order of global tile ids, part by part
   uint64_t total_tiles = 0;          // batch
   uint64_t nitems = 0;               // batch
+  std::vector<rk::Part> parts;       // one persistent launch each
 };
 
 namespace rk {
 
-struct Layout {
-  uint64_t T = 0;      // tiles
-  uint64_t T1 = 0;     // tiles per virtual instance (single plans)
-  uint32_t S = 0;      // slab slots per tile
-  uint32_t W = 0;      // tile bytes
-  uint64_t ctr = 0, inst = 0, counts = 0, offsets = 0, ovf = 0, tmp = 0, slabs = 0, total = 0;
+// One part of a count or collect pass as laid out in scratch.
+struct PartRun {
+  uint64_t tile0 = 0, ntiles = 0;  // tiles of the part in the pass's numbering
+  uint32_t W = 0;                  // tile bytes
+  uint32_t S = 0;                  // slab slots per tile
+  uint64_t slabs = 0;              // scratch offset of the part's slabs [tile][S]
 };
+
+// Scratch of a pass: counters (total at 0, per-part overflow counts at 8 + 4p,
+// per-part queue cursors at 48 + 4p), instance descriptors (single plans),
+// per-tile counts, offsets and overflow lists, scan partials, slabs.
+struct Layout {
+  uint64_t T = 0;      // tiles over all parts
+  uint64_t T1 = 0;     // tiles per virtual instance (single plans)
+  std::vector<PartRun> parts;
+  uint64_t ctr = 0, inst = 0, counts = 0, offsets = 0, ovf = 0, tmp = 0, total = 0;
+};
+constexpr uint32_t kCtrOvf = 8, kCtrQueue = 48;
+// Tiles that overflowed their slabs, summed over parts, from the first 64
+// counter bytes.
+inline uint32_t ovf_total(const uint64_t *ctr) {
+  const uint32_t *w = (const uint32_t *)ctr;
+  uint32_t t = 0;
+  for (int p = 0; p < kMaxParts; ++p) t += w[kCtrOvf / 4 + p];
+  return t;
+}
 
 rk_status set_err(rk_ctx *ctx, rk_status st, const char *fmt, ...);
 rk_status hip_err(rk_ctx *ctx, hipError_t e, const char *what);

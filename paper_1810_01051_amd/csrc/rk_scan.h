@@ -659,19 +659,42 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *wsum, 
   return before + x - v;
 }
 
-// Exact hash (canonical) of m bytes at p (LDS), Horner.
-__device__ __forceinline__ uint64_t horner_exact(const uint8_t *p, uint32_t m) {
+// The four bytes ending at *last (LDS, any alignment) as a big-endian word:
+// (last[-3] << 24) | ... | last[0], from the two aligned dwords that hold them.
+__device__ __forceinline__ uint32_t word_ending_at(const uint8_t *last) {
+  const uint8_t *a = last - 3;
+  const uint32_t mis = (uint32_t)(uintptr_t)a & 3u;
+  const uint32_t *aw = (const uint32_t *)(a - mis);
+  return __builtin_bswap32(__builtin_amdgcn_alignbyte(aw[1], aw[0], mis));
+}
+
+// Exact hash (canonical) of the m <= kStreamM bytes ending at *end (LDS):
+// Horner over big-endian words, 2^32 per word (four bytes at a time), the
+// oldest word masked to the window's bytes.  The candidate key of exact
+// buckets; equal to the value the rolling pass held for that window.
+__device__ __forceinline__ uint64_t exact_key(const uint8_t *end, uint32_t m) {
+  const uint32_t nw = (m + 3u) >> 2, lead = 4u * nw - m;  // lead: bytes of the oldest word before the window
   uint64_t s = 0;
-  for (uint32_t j = 0; j < m; ++j) s = mul256_lazy(s) + p[j];
+  for (uint32_t j = nw; j-- > 0;) {
+    uint32_t w = word_ending_at(end - 4 * j);
+    if (j == nw - 1u && lead) w &= 0xFFFFFFFFu >> (8u * lead);
+    s = mul2p32_lazy(s) + w;
+  }
   return canon(s);
 }
 
 // Shift-add hash of the span = 32/s bytes ending at *end (the value the scan's
 // screen pass held for that window end), masked as the group's hash is.
+// Four bytes at a time: each big-endian word's bytes weigh 2^(3s), ..., 1.
 __device__ __forceinline__ uint32_t screen_key(const uint8_t *end, uint32_t shift, uint32_t mask) {
-  const uint32_t span = 32u / shift;
+  const uint32_t span = 32u / shift, nw = span >> 2;
   uint32_t h = 0;
-  for (uint32_t j = span; j-- > 0;) h = (h << shift) + end[-(int)j];
+  for (uint32_t j = nw; j-- > 0;) {
+    const uint32_t w = word_ending_at(end - 4 * j);
+    const uint32_t v = ((w >> 24) << (3 * shift)) + (((w >> 16) & 0xFFu) << (2 * shift)) +
+                       (((w >> 8) & 0xFFu) << shift) + (w & 0xFFu);
+    h = j == nw - 1u ? v : (h << (4 * shift)) + v;  // (one word when shift = 8: no 32-bit shift)
+  }
   return h & mask;
 }
 
@@ -931,8 +954,7 @@ __device__ __forceinline__ void candidate_phase(Bits<C> &bits, const BucketDesc 
         if (rec1) {
           rec = rec1;  // the bucket has one key: every candidate's record
         } else {
-          const uint64_t key = screen ? (uint64_t)screen_key(end, D.shift & 0xFFu, D.mask)
-                                      : horner_exact(end - (m - 1), m);
+          const uint64_t key = screen ? (uint64_t)screen_key(end, D.shift & 0xFFu, D.mask) : exact_key(end, m);
           rec = table ? table_record(img, gimg, D, (uint32_t)key) : key_lookup(gimg, D, key);
         }
         nh = verify_run(gimg, D, rec, end, e, gtext, hmask);
@@ -1062,7 +1084,7 @@ __global__ __launch_bounds__(WG) void scan_kernel(ScanParams p) {
     const uint64_t n = cur.n;
     const int64_t tstart = cur.tstart;
     uint64_t *slab = nullptr;
-    if (p.out) slab = p.direct ? (p.out + p.tile_offsets[gt]) : (p.out + gt * (uint64_t)p.slab_cap);
+    if (p.out) slab = p.direct ? (p.out + p.tile_offsets[gt]) : (p.out + (gt - p.tile0) * (uint64_t)p.slab_cap);
     const uint32_t cap = p.direct ? 0xFFFFFFFFu : p.slab_cap;
     // Everything this tile reads from memory into registers is there before
     // the next tile's loads are issued (the compiler would otherwise wait for

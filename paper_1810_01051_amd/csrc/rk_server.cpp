@@ -372,9 +372,9 @@ static rk_status start_step(rk_server *S, Slot &sl, std::unique_lock<std::mutex>
   sl.slab_cap = 0;
   if (st == RK_OK && S->hits_per_pattern > 0 && nbytes > 0) {
     const uint64_t W = (uint64_t)kTileCfgs[sl.plan.cfg].wg * kTileCfgs[sl.plan.cfg].c;
-    // tiles of the step: every virtual instance (group of buckets sharing an
-    // image) scans the corpus once
-    const uint64_t tiles = (nbytes + W - 1) / W * std::max<uint64_t>(1, sl.plan.vinsts.size());
+    // tiles of the step: every image (m-bucket of the merged patterns) scans
+    // the corpus once
+    const uint64_t tiles = std::max<uint64_t>(1, sl.plan.total_tiles);
     const double per_tile = S->hits_per_pattern * (double)kt / (double)tiles;
     const uint64_t lo = W / 16, hi = std::min<uint64_t>(W / 2, (2ull << 30) / (8 * tiles));
     const uint64_t want = aup((uint64_t)(4.0 * per_tile) + 1, 64);
@@ -405,7 +405,7 @@ static rk_status start_step(rk_server *S, Slot &sl, std::unique_lock<std::mutex>
       if (e != hipSuccess) return hip_err(S->ctx, e, "plan upload");
       rk_status s2 = count_enqueue(S->ctx, &sl.plan, nullptr, 0, sl.scratch, sl.scratch_cap, nullptr, sl.stream);
       if (s2 != RK_OK) return s2;
-      e = hipMemcpyAsync(sl.hctr, sl.scratch, 16, hipMemcpyDeviceToHost, sl.stream);
+      e = hipMemcpyAsync(sl.hctr, sl.scratch, 64, hipMemcpyDeviceToHost, sl.stream);
       return e == hipSuccess ? RK_OK : hip_err(S->ctx, e, "count readback");
     });
   }
@@ -573,7 +573,7 @@ static void scheduler(rk_server *S) {
         const hipError_t q = hipEventQuery(sl.ev_count);
         if (q == hipSuccess) {
           sl.total = sl.hctr[0];
-          sl.ovf = (uint32_t)(sl.hctr[1] & 0xFFFFFFFFu);
+          sl.ovf = ovf_total(sl.hctr);
           sl.state = kCounted;
           progress = true;
         } else if (q != hipErrorNotReady) {

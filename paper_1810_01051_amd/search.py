@@ -93,6 +93,9 @@ class Context:
     def autotune_choice(self, mode, m: int) -> int:
         return int(self.lib.rk_autotune_choice(self.h, _mode(mode), int(m)))
 
+    def autotune_bucket_choice(self, mode, mclass: int, kclass: int) -> int:
+        return int(self.lib.rk_autotune_bucket_choice(self.h, _mode(mode), int(mclass), int(kclass)))
+
     # -------------------------------------------------------------- hashes
     def window_hashes(self, text: torch.Tensor, m: int, xs: torch.Tensor, stream=None) -> torch.Tensor:
         """Hash of text[x : x+m] for every x in xs (int64 tensor on the device)."""

@@ -274,3 +274,78 @@ def test_request_timeout(ctx, rk, corpora):
     assert timed_out >= 1
     assert srv.stats()["failed"] >= timed_out
     srv.close()
+
+
+class _DevView:
+    """A device array of the server arena seen by torch (read only here)."""
+
+    def __init__(self, ptr, n):
+        self.__cuda_array_interface__ = {"shape": (n,), "typestr": "<u8", "data": (ptr, False), "version": 2}
+
+
+def test_serving_full_size_corpora(ctx, rk):
+    """Config 5 at its real sizes: 64 resident corpora of 1 GiB, Poisson
+    request streams at 500, 2,000 and 8,000 req/s (a short window each), up
+    to 256 patterns of 4..64 bytes per request.  Every result equals a solo
+    search of the same request (compared on the device), and a seeded 1% of
+    the requests equal the CPU oracle."""
+    import threading
+    n = 1 << 30
+    corpora = [rkgen.config5_corpus(i, n) for i in range(64)]
+    torch.cuda.synchronize()
+    srv = rk.Server(ctx, arena_bytes=48 << 30, max_inflight=2, mode="screen")
+    for c in corpora:
+        srv.add_corpus(c)
+    pick = rkgen.rng(5, 777)
+    checked = oracle_checked = 0
+    for rate, window in ((500.0, 0.4), (2000.0, 0.1), (8000.0, 0.03)):
+        specs = rkgen.config5_request_specs(rate, window, n, corpora=64, seed_sub=int(rate) + 1)
+        reqs = []
+        for t, c, pats in specs:
+            ps = [corpora[c][p[0]:p[0] + p[1]].cpu().numpy().tobytes() if isinstance(p, tuple) else p
+                  for p in pats]
+            reqs.append((t, c, ps))
+        index = {}
+
+        def submit():
+            t0 = time.perf_counter()
+            for i, (t, c, ps) in enumerate(reqs):
+                d = t0 + t - time.perf_counter()
+                if d > 0:
+                    time.sleep(d)
+                index[srv.submit(c, ps)] = i
+
+        th = threading.Thread(target=submit)
+        th.start()
+        sample = set(pick.choice(len(reqs), size=max(1, len(reqs) // 100), replace=False).tolist())
+        for _ in range(len(reqs)):
+            rid = srv.next_done(timeout=120.0)
+            assert rid is not None
+            while rid not in index:
+                time.sleep(0.0005)
+            i = index[rid]
+            t, c, ps = reqs[i]
+            res = srv.wait(rid, timeout=0.0, fetch=False)
+            assert res["status"] == 0, (rate, i)
+            tot = int(res["offsets"][-1])
+            plan = rk.Plan(ctx, ps, "screen")
+            so, sp = plan.search(corpora[c])
+            torch.cuda.synchronize()
+            plan.close()
+            assert res["offsets"].tolist() == so.cpu().numpy().astype(np.uint64).tolist(), (rate, i)
+            if tot:
+                got = torch.as_tensor(_DevView(res["positions_dev"], tot), device="cuda:0")
+                assert torch.equal(got.view(torch.int64), sp[:tot]), (rate, i)
+            if i in sample:
+                ro, rp = oracle.search(corpora[c].cpu().numpy(), ps, threads=16)
+                assert res["offsets"].tolist() == ro.tolist(), (rate, i)
+                assert sp.cpu().numpy().astype(np.uint64).tolist() == rp.tolist(), (rate, i)
+                oracle_checked += 1
+            srv.release(rid)
+            checked += 1
+        th.join()
+    st = srv.stats()
+    assert st["failed"] == 0 and st["completed"] == checked
+    assert oracle_checked >= 3
+    srv.close()
+    del corpora
