@@ -573,8 +573,9 @@ def bench_config5(args):
     # the baseline: one request per step, one step at a time, plain launches,
     # on the same request stream at every offered rate
     for rate in ([] if args.no_unbatched else args.rates):
-        results["one_request_per_launch_%d" % rate] = run(rate, args.warm5, args.duration5, arena_bytes=args.arena,
-                                                          max_inflight=1, max_step_requests=1, use_graphs=False)
+        results["one_request_per_launch_%d" % rate] = run(rate, args.warm5, args.duration5_base or args.duration5,
+                                                          arena_bytes=args.arena, max_inflight=1,
+                                                          max_step_requests=1, use_graphs=False)
         log("config5 unbatched %d: %s" % (rate, results["one_request_per_launch_%d" % rate]))
     top = results["batched_%d" % max(args.rates)]
     line = {
@@ -680,6 +681,63 @@ def bench_paper(args):
         log("paper m %d: %.3f ms, tiled %s" % (m, ms, tiled))
 
 
+# ---------------------------------------------------------------- streamed
+def bench_stream(args):
+    """A text in host memory (pageable, args.stream_n bytes of i.i.d. ACGT)
+    searched by rk_search_host in pieces of args.piece bytes: link-bound
+    end-to-end GB/s (staging, host-to-device copy and search overlapped), with
+    the same text resident on the device for comparison.  The result is
+    checked against the device-resident search."""
+    import numpy as np
+    import torch
+    import rkgen
+    import paper_1810_01051_amd as rk
+    n = args.stream_n
+    t0 = time.perf_counter()
+    s = rkgen.config2(n=n, plants=1000)
+    log("stream: %d bytes generated in %.1fs" % (n, time.perf_counter() - t0))
+    ctx = make_ctx(rk, args)
+    res = {}
+    for mode in ("screen", "exact"):
+        plan = rk.Plan(ctx, s.patterns, mode)
+        plan.search_host(s.text[:1 << 26], args.piece)  # warm-up
+        ts = []
+        for _ in range(max(1, args.steps // 5)):
+            t0 = time.perf_counter()
+            off, pos = plan.search_host(s.text, args.piece)
+            ts.append(time.perf_counter() - t0)
+        el = min(ts)
+        text = torch.from_numpy(s.text).to("cuda:0")
+        ro, rp = plan.search(text)
+        torch.cuda.synchronize()
+        same = off.tolist() == ro.cpu().numpy().astype(np.uint64).tolist() and \
+            pos.tolist() == rp.cpu().numpy().astype(np.uint64).tolist()
+        del text
+        torch.cuda.empty_cache()
+        plan.close()
+        res[mode] = {"GB/s": round(n / el / 1e9, 2), "s": round(el, 3), "hits": int(off[-1]),
+                     "same_as_resident": bool(same)}
+        log("stream %s: %s" % (mode, res[mode]))
+    # host-to-device copy ceiling over the same link (pinned source)
+    pin = torch.empty(1 << 30, dtype=torch.uint8, pin_memory=True)
+    dst = torch.empty(1 << 30, dtype=torch.uint8, device="cuda:0")
+    dst.copy_(pin, non_blocking=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(4):
+        dst.copy_(pin, non_blocking=True)
+    torch.cuda.synchronize()
+    h2d = 4 * (1 << 30) / (time.perf_counter() - t0) / 1e9
+    line = {"metric": "GB/s text scanned, streamed from host memory", "value": res["screen"]["GB/s"],
+            "unit": "GB/s", "n_gpus": 1, "steps": max(1, args.steps // 5), "warmup": 1,
+            "ms_per_step": round(res["screen"]["s"] * 1e3, 1), "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+            "config": {"workload": "streamed search: %d B i.i.d. ACGT text in pageable host memory, m=32, "
+                                   "pieces of %d B" % (n, args.piece), "results": res,
+                       "h2d_copy_GBps_pinned": round(h2d, 1)}}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -693,11 +751,13 @@ def main():
     ap.add_argument("--cfg", type=int, default=-1, help="force a scan geometry (rk_tile_cfg index)")
     ap.add_argument("--grid", type=int, default=0, help="force the persistent grid size")
     ap.add_argument("--workload", default="config2",
-                    choices=["config1", "config2", "config3", "config4", "config5", "paper"],
+                    choices=["config1", "config2", "config3", "config4", "config5", "paper", "stream"],
                     help="config2 (default): the single-pattern DNA scan; config1: the 1 MiB latency case; config3: "
                          "1,024 patterns over Zipf text; config4: batched uneven instances; config5: serving; "
                          "paper: the paper's Tables 1-3 in paper mode")
     ap.add_argument("--paper-n", type=int, default=320 * 10 ** 6, help="paper workload text bytes")
+    ap.add_argument("--stream-n", type=int, default=16 << 30, help="stream workload host text bytes")
+    ap.add_argument("--piece", type=int, default=512 << 20, help="stream workload piece bytes")
     ap.add_argument("--count4", type=int, default=4096, help="config4 instances")
     ap.add_argument("--patterns3", default="all", choices=["all", "sampled", "random"],
                     help="config3: every pattern, or only the sampled / only the random half")
@@ -706,6 +766,8 @@ def main():
     ap.add_argument("--rates", type=float, nargs="+", default=[500, 2000, 8000], help="config5 offered req/s")
     ap.add_argument("--warm5", type=float, default=1.0)
     ap.add_argument("--duration5", type=float, default=10.0)
+    ap.add_argument("--duration5-base", type=float, default=None,
+                    help="config5: measured window of the one-request-per-launch baseline (default: --duration5)")
     ap.add_argument("--arena", type=int, default=64 << 30, help="config5 server output arena bytes")
     ap.add_argument("--inflight", type=int, default=2, help="config5 steps in flight")
     ap.add_argument("--step-patterns", type=int, default=None,
@@ -745,6 +807,8 @@ def main():
         return bench_config5(args)
     if args.workload == "paper":
         return bench_paper(args)
+    if args.workload == "stream":
+        return bench_stream(args)
 
     import rkgen
     import paper_1810_01051_amd as rk

@@ -88,7 +88,9 @@ typedef struct rk_plan rk_plan;
 
 /* ------------------------------------------------------------------ context */
 
-/* Create a context on HIP device `device` for base d and modulus q.  Only
+/* Create a context on HIP device `device` for base d and modulus q (the
+ * parameters of the polynomial hash of Sec. 3.1; the paper's own are d = 2
+ * with no modulus, see rk_paper_search).  Only
  * d = 256 and q = 2^61 - 1 are supported (RK_EUNSUPPORTED otherwise); the
  * arguments exist so that the hash parameters are explicit at the boundary.
  * *out receives the context.  Makes `device` current on the calling thread. */
@@ -145,6 +147,8 @@ void rk_plan_destroy(rk_plan *plan);
 uint32_t rk_plan_patterns(const rk_plan *plan);
 
 /* Bytes of device scratch that rk_count / rk_collect need for a text of n
+ * (per-tile staging of hits, which replaces the dense result array of
+ * Sec. 3.1)
  * bytes (a function of n, the plan and RK_OPT_SLAB_CAP). */
 rk_status rk_scratch_size(rk_ctx *ctx, const rk_plan *plan, uint64_t n, uint64_t *bytes);
 
@@ -164,7 +168,9 @@ rk_status rk_count(rk_ctx *ctx, const rk_plan *plan, const uint8_t *text_dev, ui
  * (0 for single-pattern plans). */
 rk_status rk_work_size(rk_ctx *ctx, const rk_plan *plan, uint64_t total, uint64_t *bytes);
 
-/* Collect pass, after rk_count with the same plan, text and scratch: writes
+/* Collect pass (the second half of Sec. 1's problem: the occurrences
+ * themselves, in place of the GPU procedure's dense result array of Sec. 3.1),
+ * after rk_count with the same plan, text and scratch: writes
  * offsets_dev[0..k] (offsets_dev[j+1] - offsets_dev[j] = hits of pattern j,
  * offsets_dev[0] = 0) and positions_dev[offsets[j] .. offsets[j+1]) = pattern
  * j's positions, strictly ascending.  capacity = entries of positions_dev
@@ -173,7 +179,9 @@ rk_status rk_collect(rk_ctx *ctx, const rk_plan *plan, const uint8_t *text_dev, 
                      void *scratch_dev, uint64_t scratch_bytes, void *work_dev, uint64_t work_bytes,
                      uint64_t *offsets_dev, uint64_t *positions_dev, uint64_t capacity, rk_stream s);
 
-/* Window hashes: out_dev[i] = hash(text_dev[xs_dev[i] .. xs_dev[i]+m)) in [0, q),
+/* Window hashes (Sec. 3.1: the hash hy of the substring at offset x, here
+ * with d = 256, q = 2^61 - 1):
+ * out_dev[i] = hash(text_dev[xs_dev[i] .. xs_dev[i]+m)) in [0, q),
  * each evaluated directly (Horner) on the device.  Every xs_dev[i] must satisfy
  * xs + m <= n; out-of-range entries get the value UINT64_MAX. */
 rk_status rk_window_hashes(rk_ctx *ctx, const uint8_t *text_dev, uint64_t n, uint32_t m,
@@ -296,8 +304,12 @@ typedef struct {
   uint32_t k;
 } rk_instance;
 
-/* Plan for `count` independent searches scanned by one persistent launch over
- * a work queue of tiles ordered by pattern-length bucket.  Instance i's
+/* Plan for `count` independent searches (each the problem of Sec. 1 on its
+ * own text; the paper runs one search per launch, Sec. 3.1) scanned by
+ * persistent launches (one per scan geometry in use), each over an atomic
+ * work queue of (instance, pattern-length bucket, tile) items ordered by
+ * bucket; each bucket's geometry comes from the autotuner's table
+ * (rk_autotune / rk_autotune_load).  Instance i's
  * patterns get global ids base_i + j with base_i = sum of k over instances
  * before i.  The plan keeps the text pointers; the texts must stay alive and
  * unchanged while the plan is used. */

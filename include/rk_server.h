@@ -28,6 +28,12 @@
  *
  * Results are exact and identical to a solo rk_count/rk_collect of the same
  * request: merging only changes which patterns share a scan.
+ *
+ * While the server captures a step, work that a client enqueues on the
+ * legacy default stream of the same device may be refused by the runtime
+ * (the legacy stream would wait on a capturing stream): clients that work on
+ * the device beside a running server use streams of their own (the library's
+ * own uploads, rk_plan_create included, never use the legacy stream).
  */
 #ifndef RK_SERVER_H
 #define RK_SERVER_H
@@ -99,14 +105,16 @@ typedef struct {
   uint64_t step_splits;        /* counted steps given back to the queue as too large */
 } rk_server_stats;
 
-/* Creates a server on ctx's device.  The server owns its streams, graphs,
+/* Creates a server on ctx's device (batches of Sec. 1's problem on resident
+ * texts; the paper runs one search per launch, Sec. 3.1).  The server owns its streams, graphs,
  * arena and scheduler thread; ctx must outlive it and is not used by the
  * server's thread (the server keeps its own context on the same device). */
 rk_status rk_server_create(rk_ctx *ctx, const rk_server_cfg *cfg, rk_server **out);
 /* Registers a resident corpus (device memory, 16-byte aligned, caller-owned,
  * unchanged while the server runs).  Thread-safe. */
 rk_status rk_server_add_corpus(rk_server *srv, const uint8_t *text_dev, uint64_t n, uint32_t *corpus_id);
-/* Queues a search of corpus_id for k patterns (host arrays, copied).
+/* Queues a search of corpus_id for k patterns (host arrays, copied): every
+ * occurrence of every pattern, as rk_count + rk_collect would give (Sec. 1).
  * Thread-safe.  Pattern lengths as in rk.h. */
 rk_status rk_server_submit(rk_server *srv, uint32_t corpus_id, const uint8_t *bytes_host,
                            const uint64_t *offsets_host, uint32_t k, uint64_t *req_id);

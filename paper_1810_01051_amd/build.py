@@ -8,6 +8,7 @@ single translation unit dominates), then link into one shared library.
 """
 from __future__ import annotations
 
+import json
 import os
 import subprocess
 import sys
@@ -44,6 +45,38 @@ def _jobs() -> int:
     return max(1, min(n, 16))
 
 
+def _resource_usage(out: str) -> dict:
+    """Per-kernel resource usage from the compiler's kernel-resource-usage
+    remarks: VGPRs, SGPRs, scratch bytes per lane, dynamic stack, occupancy."""
+    kernels, cur = {}, None
+    for line in out.splitlines():
+        if "kernel-resource-usage" not in line:
+            continue
+        body = line.split("remark:", 1)[-1].split("[-Rpass", 1)[0].strip()
+        key, _, val = body.partition(":")
+        key, val = key.strip(), val.strip()
+        if key == "Function Name":
+            cur = kernels.setdefault(val, {})
+        elif cur is not None:
+            if key == "VGPRs":
+                cur["vgprs"] = int(val)
+            elif key == "TotalSGPRs":
+                cur["sgprs"] = int(val)
+            elif key.startswith("ScratchSize"):
+                cur["scratch"] = int(val)
+            elif key == "Dynamic Stack":
+                cur["dyn_stack"] = val.lower() == "true"
+            elif key.startswith("Occupancy"):
+                cur["occupancy"] = int(val)
+            elif key.startswith("LDS Size"):
+                cur["lds"] = int(val)
+            elif key == "VGPRs Spill":
+                cur["vgpr_spill"] = int(val)
+            elif key == "SGPRs Spill":
+                cur["sgpr_spill"] = int(val)
+    return kernels
+
+
 def _stale(src: str, obj: str) -> bool:
     """True if obj is missing or older than src or any header of csrc/ and include/."""
     if not os.path.exists(obj):
@@ -65,19 +98,33 @@ def build(verbose: bool = False, only_stale: bool = False) -> str:
 
     def one(src):
         obj = os.path.join(objdir, src + ".o")
-        if only_stale and not _stale(src, obj):
-            return obj, ""
-        lang = ["-x", "hip"] if src.endswith(".hip") else []
+        usage = obj + ".usage.json"
+        if only_stale and not _stale(src, obj) and os.path.exists(usage):
+            return obj, "", json.load(open(usage))
+        hip = src.endswith(".hip")
+        lang = ["-x", "hip", "-Rpass-analysis=kernel-resource-usage"] if hip else []
         cmd = ["hipcc", "--offload-arch=" + ARCH] + FLAGS + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
-        return obj, _run(cmd)
+        out = _run(cmd)
+        kernels = _resource_usage(out) if hip else {}
+        json.dump(kernels, open(usage, "w"), indent=1, sort_keys=True)
+        msg = "\n".join(l for l in out.splitlines() if "kernel-resource-usage" not in l)
+        return obj, msg, kernels
 
     with ThreadPoolExecutor(max_workers=_jobs()) as ex:
         results = list(ex.map(one, SOURCES))
-    objs = []
-    for obj, msg in results:
+    objs, kernels = [], {}
+    for obj, msg, k in results:
         if verbose and msg.strip():
             print(msg)
         objs.append(obj)
+        kernels.update(k)
+    json.dump(kernels, open(os.path.join(objdir, "resource_usage.json"), "w"), indent=1, sort_keys=True)
+    # no kernel may keep anything on a per-lane stack (a called, outlined
+    # function or a spilled array): the scans read LDS through addresses
+    # they form themselves and must stay one straight-line kernel
+    stack = sorted(k for k, v in kernels.items() if v.get("scratch", 0) or v.get("dyn_stack") or v.get("vgpr_spill", 0))
+    if stack:
+        raise RuntimeError("kernels with a private-segment stack: " + ", ".join(stack))
     tmp = LIB + ".tmp%d" % os.getpid()
     _run(["hipcc", "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs)
     os.replace(tmp, LIB)

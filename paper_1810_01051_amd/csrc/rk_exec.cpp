@@ -221,12 +221,15 @@ rk_status plan_build(rk_ctx *ctx, const rk_instance *inst, uint32_t count, int m
   P->blob_dev = (uint8_t *)P->dev;
   P->inst_dev = descs.empty() ? nullptr : (InstDesc *)((uint8_t *)P->dev + blob_bytes);
   P->items_dev = items.empty() ? nullptr : (uint64_t *)((uint8_t *)P->dev + blob_bytes + desc_bytes);
+  // uploads on the context's own non-blocking stream: never the legacy
+  // stream, which must not wait on a stream another thread is capturing
   hipError_t e = hipSuccess;
-  if (!blob.empty()) e = hipMemcpy(P->blob_dev, blob.data(), blob.size(), hipMemcpyHostToDevice);
+  if (!blob.empty()) e = hipMemcpyAsync(P->blob_dev, blob.data(), blob.size(), hipMemcpyHostToDevice, ctx->aux);
   if (e == hipSuccess && !descs.empty())
-    e = hipMemcpy(P->inst_dev, descs.data(), descs.size() * sizeof(InstDesc), hipMemcpyHostToDevice);
+    e = hipMemcpyAsync(P->inst_dev, descs.data(), descs.size() * sizeof(InstDesc), hipMemcpyHostToDevice, ctx->aux);
   if (e == hipSuccess && !items.empty())
-    e = hipMemcpy(P->items_dev, items.data(), items.size() * 8, hipMemcpyHostToDevice);
+    e = hipMemcpyAsync(P->items_dev, items.data(), items.size() * 8, hipMemcpyHostToDevice, ctx->aux);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->aux);
   if (e != hipSuccess) {
     rk_status st2 = hip_err(ctx, e, "plan upload");
     hipFree(P->dev);

@@ -501,6 +501,11 @@ rk_status rk_ctx_create(int device, uint64_t d, uint64_t q, rk_ctx **out) {
     delete c;
     return RK_ENOMEM;
   }
+  if (hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess) {
+    hipHostFree(c->pinned);
+    delete c;
+    return RK_EDEVICE;
+  }
   for (int md = 0; md < 3; ++md) {
     for (int m = 0; m <= RK_MAX_M; ++m) c->tune[md][m] = -1;
     for (int a = 0; a < kNumMClass; ++a)
@@ -508,6 +513,7 @@ rk_status rk_ctx_create(int device, uint64_t d, uint64_t q, rk_ctx **out) {
   }
   prepare_scan_kernels();
   if (static_scratch_setup(c) != RK_OK) {
+    hipStreamDestroy(c->aux);
     hipHostFree(c->pinned);
     delete c;
     return RK_EDEVICE;
@@ -524,6 +530,7 @@ void rk_ctx_destroy(rk_ctx *ctx) {
     hipEventDestroy(ev.b);
   }
   if (ctx->pinned) hipHostFree(ctx->pinned);
+  if (ctx->aux) hipStreamDestroy(ctx->aux);
   delete ctx;
 }
 

@@ -80,6 +80,7 @@ struct rk_ctx {
   bool profile = false;
   int queue = -1;
   uint64_t *pinned = nullptr;  // 4 KiB of pinned host memory for small transfers
+  hipStream_t aux = nullptr;   // the context's own non-blocking stream (plan uploads)
   std::vector<uint8_t> upload; // staging for instance descriptors
   std::vector<rk::ProfEvent> prof_events, free_events;
   int tune[3][RK_MAX_M + 1];

@@ -385,17 +385,38 @@ __device__ __forceinline__ bool in_cuckoo(const uint32_t *tab, uint32_t sh, uint
   return (tab[ck_slot1(h, sh)] == h) | (tab[ck_slot2(h, sh)] == h);
 }
 
+// Windows per block of the table tests: the LDS probes of a block's windows
+// are all issued before the first of them is compared, so that their
+// latencies overlap (C is a multiple of 4 in every geometry).
+constexpr int kProbeBlock = 4;
+
 template <int C, int S, bool ANY>
 __device__ __forceinline__ void pass_table_screen_w(const uint32_t *w, uint32_t msk, const uint32_t *tab, uint32_t sh,
                                                     uint64_t &any, Bits<C> &bits) {
+  static_assert(C % kProbeBlock == 0, "whole probe blocks");
   uint32_t h = screen_init<S>(w), acc = 0;
 #pragma unroll
-  for (int i = 0; i < C; ++i) {
-    h = (h << S) + byte_at(w, 64 + i);
-    const uint32_t v = (S == 8) ? (h & msk) : h;
-    const bool c = in_cuckoo(tab, sh, v);
-    if (ANY) any_or(any, ballot(c));
-    else put_bit<C>(bits, acc, i, c);
+  for (int i0 = 0; i0 < C; i0 += kProbeBlock) {
+    uint32_t v[kProbeBlock], t1[kProbeBlock], t2[kProbeBlock];
+#pragma unroll
+    for (int j = 0; j < kProbeBlock; ++j) {
+      h = (h << S) + byte_at(w, 64 + i0 + j);
+      v[j] = (S == 8) ? (h & msk) : h;
+    }
+#pragma unroll
+    for (int j = 0; j < kProbeBlock; ++j) {
+      t1[j] = tab[ck_slot1(v[j], sh)];
+      t2[j] = tab[ck_slot2(v[j], sh)];
+    }
+    if (ANY) {
+      uint64_t b = 0;
+#pragma unroll
+      for (int j = 0; j < kProbeBlock; ++j) b |= ballot(t1[j] == v[j]) | ballot(t2[j] == v[j]);
+      any_or(any, b);
+    } else {
+#pragma unroll
+      for (int j = 0; j < kProbeBlock; ++j) put_bit<C>(bits, acc, i0 + j, (t1[j] == v[j]) | (t2[j] == v[j]));
+    }
   }
 }
 
@@ -420,7 +441,8 @@ __device__ __forceinline__ uint64_t exact_init(const uint32_t *w, uint32_t m) {
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
     const int lead = 64 - (int)m - 4 * q;  // bytes of this word that precede the window
-    const uint32_t keep = lead <= 0 ? 0xFFFFFFFFu : (lead >= 4 ? 0u : (0xFFFFFFFFu >> (8 * lead)));
+    if (lead >= 4) continue;                // wholly before the window: s stays 0 (m is uniform)
+    const uint32_t keep = lead <= 0 ? 0xFFFFFFFFu : (0xFFFFFFFFu >> (8 * lead));
     s = mul2p32_lazy(s) + (__builtin_bswap32(w[q]) & keep);
   }
   return s;
@@ -715,15 +737,15 @@ __device__ __forceinline__ uint64_t key_lookup(const uint8_t *gimg, const Bucket
 
 // Record of the 32-bit key h of a table bucket: the cuckoo slot holding h
 // (LDS) indexes the per-slot records in device memory; 0 if h is no key.
+// Branch-free (both slots probed, the record of one of them loaded), so that
+// the lookups of several candidates overlap.
 __device__ __forceinline__ uint64_t table_record(const uint8_t *img, const uint8_t *gimg, const BucketDesc &D,
                                                  uint32_t h) {
   const uint32_t *tab = (const uint32_t *)(img + D.fp_off);
-  uint32_t s = ck_slot1(h, D.fp_mask);
-  if (tab[s] != h) {
-    s = ck_slot2(h, D.fp_mask);
-    if (tab[s] != h) return 0;
-  }
-  return ((const uint64_t *)(gimg + D.ht_off))[s];
+  const uint32_t s1 = ck_slot1(h, D.fp_mask), s2 = ck_slot2(h, D.fp_mask);
+  const bool in1 = tab[s1] == h, in2 = tab[s2] == h;
+  const uint64_t rec = ((const uint64_t *)(gimg + D.ht_off))[in1 ? s1 : s2];
+  return (in1 || in2) ? rec : 0;
 }
 
 // Compares the m bytes ending at *end (LDS tile, any alignment) with the
@@ -886,7 +908,7 @@ __device__ __forceinline__ void dma_tile(uint8_t *slot, const uint8_t *text, uin
 // device image gimg), byte comparison with every pattern of the record.  Hits
 // go to the tile's slab (up to cap records) in window order; tile_hits counts
 // them all.  ncand returns the number of candidates (block-uniform).
-template <int WG, int C>
+template <int WG, int C, bool PAIR>
 __device__ __forceinline__ void candidate_phase(Bits<C> &bits, const BucketDesc &D, const uint8_t *tile, int64_t tstart,
                                                 uint64_t n, int64_t e0, const uint8_t *img, const uint8_t *gimg,
                                                 uint32_t *cand,
@@ -939,33 +961,66 @@ __device__ __forceinline__ void candidate_phase(Bits<C> &bits, const BucketDesc 
     }
     wg_barrier();
     const uint32_t nc = min(kCandCap, ncand - r0);
-    for (uint32_t i0 = 0; i0 < nc; i0 += WG) {
-      const uint32_t ci = i0 + tid;
-      uint64_t rec = 0;
-      uint32_t nh = 0, hmask = 0;
-      const uint8_t *end = nullptr;
-      int64_t e = 0;
-      const bool screen = D.kind == kListScreen || D.kind == kTableScreen;
-      const bool table = D.kind == kTableScreen || D.kind == kTableExact;
-      if (ci < nc) {
-        const uint32_t e_rel = cand[ci];
-        end = tile + kFront + e_rel;
-        e = tstart + (int64_t)e_rel;
-        if (rec1) {
-          rec = rec1;  // the bucket has one key: every candidate's record
-        } else {
-          const uint64_t key = screen ? (uint64_t)screen_key(end, D.shift & 0xFFu, D.mask) : exact_key(end, m);
-          rec = table ? table_record(img, gimg, D, (uint32_t)key) : key_lookup(gimg, D, key);
+    const bool screen = D.kind == kListScreen || D.kind == kTableScreen;
+    const bool table = D.kind == kTableScreen || D.kind == kTableExact;
+    // PAIR: two adjacent candidates per thread, both records looked up
+    // before either is verified, so that their loads overlap (the pair keeps
+    // the candidates' order in the block scan of hit counts); otherwise one
+    // candidate per thread (fewer registers: the exact family keeps its
+    // occupancy).
+    auto record_of = [&](uint32_t ci, const uint8_t *&end, int64_t &e) __attribute__((always_inline)) -> uint64_t {
+      const uint32_t e_rel = cand[ci];
+      end = tile + kFront + e_rel;
+      e = tstart + (int64_t)e_rel;
+      if (rec1) return rec1;  // the bucket has one key: every candidate's record
+      const uint64_t key = screen ? (uint64_t)screen_key(end, D.shift & 0xFFu, D.mask) : exact_key(end, m);
+      return table ? table_record(img, gimg, D, (uint32_t)key) : key_lookup(gimg, D, key);
+    };
+    if constexpr (PAIR) {
+      for (uint32_t i0 = 0; i0 < nc; i0 += 2 * WG) {
+        const uint32_t ca = i0 + 2 * tid, cb = ca + 1;
+        const bool va = ca < nc, vb = cb < nc;
+        const uint8_t *enda, *endb;
+        int64_t ea, eb;
+        // out-of-range lanes look up the last candidate and drop the result
+        uint64_t reca = record_of(va ? ca : nc - 1, enda, ea);
+        uint64_t recb = record_of(vb ? cb : nc - 1, endb, eb);
+        if (!va) reca = 0;
+        if (!vb) recb = 0;
+        uint32_t ma = 0, mb = 0;
+        const uint32_t nha = reca ? verify_run(gimg, D, reca, enda, ea, gtext, ma) : 0;
+        const uint32_t nhb = recb ? verify_run(gimg, D, recb, endb, eb, gtext, mb) : 0;
+        uint32_t nht;
+        const uint32_t hb = block_excl_scan<WG>(nha + nhb, misc, nht);
+        if (nha) {
+          uint32_t o = tile_hits + hb;
+          write_hits(gimg, D, reca, ma, enda, ea, gtext, slab, cap, o, pid_counts);
         }
-        nh = verify_run(gimg, D, rec, end, e, gtext, hmask);
+        if (nhb) {
+          uint32_t o = tile_hits + hb + nha;
+          write_hits(gimg, D, recb, mb, endb, eb, gtext, slab, cap, o, pid_counts);
+        }
+        tile_hits += nht;
       }
-      uint32_t nht;
-      const uint32_t hb = block_excl_scan<WG>(nh, misc, nht);
-      if (nh) {
-        uint32_t o = tile_hits + hb;
-        write_hits(gimg, D, rec, hmask, end, e, gtext, slab, cap, o, pid_counts);
+    } else {
+      for (uint32_t i0 = 0; i0 < nc; i0 += WG) {
+        const uint32_t ci = i0 + tid;
+        const uint8_t *end = tile;
+        int64_t e = 0;
+        uint64_t rec = 0;
+        uint32_t nh = 0, hmask = 0;
+        if (ci < nc) {
+          rec = record_of(ci, end, e);
+          nh = verify_run(gimg, D, rec, end, e, gtext, hmask);
+        }
+        uint32_t nht;
+        const uint32_t hb = block_excl_scan<WG>(nh, misc, nht);
+        if (nh) {
+          uint32_t o = tile_hits + hb;
+          write_hits(gimg, D, rec, hmask, end, e, gtext, slab, cap, o, pid_counts);
+        }
+        tile_hits += nht;
       }
-      tile_hits += nht;
     }
   }
 }
@@ -1152,7 +1207,8 @@ __global__ __launch_bounds__(WG) void scan_kernel(ScanParams p) {
         uint64_t dummy = 0;
         run_pass<C, false, FAM>(D, tw, os, r, (const uint32_t *)(img + D.fp_off), dummy, bits);
         uint32_t ncand;
-        candidate_phase<WG, C>(bits, D, tile, tstart, n, e0, img, gimg, cand, misc, slab, cap, tile_hits, ncand,
+        candidate_phase<WG, C, FAM != kFamExact>(bits, D, tile, tstart, n, e0, img, gimg, cand, misc, slab, cap,
+                                                     tile_hits, ncand,
                                cur.text, p.direct ? nullptr : p.pid_counts);
         if (b < 32) dense_mask = ncand >= kDenseCand ? (dense_mask | (1u << b)) : (dense_mask & ~(1u << b));
       }
@@ -1246,7 +1302,7 @@ __global__ __launch_bounds__(WG) void scan_list_kernel(ListParams p) {
       uint64_t dummy = 0;
       run_pass<C, false, FAM, true>(D, tw, os, r, nullptr, dummy, bits, &pre);
       uint32_t ncand;
-      candidate_phase<WG, C>(bits, D, tile, tstart, p.n, e0, nullptr, p.gimg, cand, misc,
+      candidate_phase<WG, C, FAM != kFamExact>(bits, D, tile, tstart, p.n, e0, nullptr, p.gimg, cand, misc,
                              p.out + t * (uint64_t)p.slab_cap, p.slab_cap, tile_hits, ncand, p.text, p.pid_counts,
                              p.rec1);
       dense = ncand >= kDenseCand;

@@ -50,6 +50,7 @@ struct Outcome {
 
 // One candidate: a full search (count + collect) for the hit record, then
 // the count pass timed with the context's launch events over several runs
+// (everything on the context's own stream, readbacks included)
 // (the minimum is kept; host round trips between launches do not enter).
 // batch: the plan is a one-instance batch plan (general kernel, bucketed
 // queue); otherwise a single-text plan.
@@ -82,18 +83,20 @@ static rk_status time_one(rk_ctx *ctx, int mode, int cfg, bool batch, const uint
     return set_err(ctx, RK_ENOMEM, "autotune buffers");
   }
   uint64_t total = 0, wb = 0;
-  st = rk_count(ctx, plan, t, n, scratch.p, sb, nullptr, &total, nullptr);
+  st = rk_count(ctx, plan, t, n, scratch.p, sb, nullptr, &total, (rk_stream)ctx->aux);
   if (st == RK_OK) {
     rk_work_size(ctx, plan, total, &wb);
     if (pos.alloc(total * 8 + 8) != hipSuccess || work.alloc(wb) != hipSuccess)
       st = set_err(ctx, RK_ENOMEM, "autotune output");
   }
   if (st == RK_OK)
-    st = rk_collect(ctx, plan, t, n, scratch.p, sb, work.p, wb, (uint64_t *)offd.p, (uint64_t *)pos.p, total, nullptr);
+    st = rk_collect(ctx, plan, t, n, scratch.p, sb, work.p, wb, (uint64_t *)offd.p, (uint64_t *)pos.p, total,
+                    (rk_stream)ctx->aux);
   if (st == RK_OK) {
     std::vector<uint64_t> ho(k + 1), hp(total);
-    if (hipMemcpy(ho.data(), offd.p, (k + 1) * 8, hipMemcpyDeviceToHost) != hipSuccess ||
-        (total && hipMemcpy(hp.data(), pos.p, total * 8, hipMemcpyDeviceToHost) != hipSuccess))
+    if (hipMemcpyAsync(ho.data(), offd.p, (k + 1) * 8, hipMemcpyDeviceToHost, ctx->aux) != hipSuccess ||
+        (total && hipMemcpyAsync(hp.data(), pos.p, total * 8, hipMemcpyDeviceToHost, ctx->aux) != hipSuccess) ||
+        hipStreamSynchronize(ctx->aux) != hipSuccess)
       st = set_err(ctx, RK_EDEVICE, "autotune readback");
     out->hits = total;
     out->digest = digest_of(ho, hp);
@@ -103,7 +106,7 @@ static rk_status time_one(rk_ctx *ctx, int mode, int cfg, bool batch, const uint
     rk_ctx_profile_reset(ctx);
     ctx->profile = true;
     for (int rep = 0; rep < 6 && st == RK_OK; ++rep)
-      st = rk_count(ctx, plan, t, n, scratch.p, sb, nullptr, &total, nullptr);
+      st = rk_count(ctx, plan, t, n, scratch.p, sb, nullptr, &total, (rk_stream)ctx->aux);
     // several parts (geometries) cannot occur: the geometry is forced
     double best = 1e30;
     for (auto &ev : ctx->prof_events) {
@@ -194,7 +197,8 @@ rk_status tune_run(rk_ctx *ctx, uint64_t n, const uint32_t *lengths, uint32_t nl
   }
   DevBuf text;
   if (text.alloc(n) != hipSuccess) return set_err(ctx, RK_ENOMEM, "autotune text");
-  if (hipMemcpy(text.p, host.data(), n, hipMemcpyHostToDevice) != hipSuccess)
+  if (hipMemcpyAsync(text.p, host.data(), n, hipMemcpyHostToDevice, ctx->aux) != hipSuccess ||
+      hipStreamSynchronize(ctx->aux) != hipSuccess)
     return set_err(ctx, RK_EDEVICE, "autotune upload");
   std::vector<std::string> rows, brows;
   char row[256];
