@@ -65,6 +65,12 @@ typedef enum {
 /* Scan modes.  Both give identical results.
  *   RK_MODE_EXACT : every window's d=256 / q=2^61-1 hash is rolled and tested
  *                   against the pattern-hash set; equal hashes are byte-checked.
+ *                   A set whose lengths all agree (one pattern, say) hashes
+ *                   whole windows.  Several lengths share one stream per
+ *                   length class (1, 2, 3, 4..7, 8..15, 16..31, 32 and more):
+ *                   it hashes the last l bytes of every window, l the shortest
+ *                   length of the class (at most RK_STREAM_M), and each
+ *                   pattern is keyed by the hash of its last l bytes.
  *   RK_MODE_SCREEN: every window gets a shift-and-add hash in the paper's form
  *                   h <- (h << s) + c taken mod 2^32 (the polynomial hash
  *                   with d = 2^s, q = 2^32) with s = 8 for patterns shorter

@@ -123,28 +123,41 @@ __global__ __launch_bounds__(256) void compact_slabs(const uint32_t *counts, con
 
 // -------------------------------------------------- stable radix by pattern id
 // Records are pid << 40 | x.  One DB-bit digit of the pid per pass (8 bits,
-// or 11 when a single 11-bit pass covers every pid); a block is one wave
-// walking its BLK records 64 at a time in order, so ranks are stable.
+// or 9..11 when a single pass covers every pid); a block is one wave walking
+// its BLK records in order, so ranks are stable.  Each lane loads kRadixR
+// records before it handles any, so that a wave keeps kRadixR * 64 loads in
+// flight instead of one round trip per 64 records.
 constexpr int kRadixBlock = 1024;        // records per block, 8-bit digits
-constexpr int kRadixBlock11 = 8192;      // records per block, 11-bit digits (same histogram size)
+constexpr int kRadixBlock11 = 8192;      // records per block, 9..11-bit digits (at most 2048 digits per block)
+constexpr int kRadixR = 8;               // records per lane in flight
 
 template <int DB, int BLK>
 __global__ __launch_bounds__(64) void radix_hist(const uint64_t *in, uint64_t n, uint32_t shift, uint32_t *ghist,
                                                  uint64_t nblk) {
   constexpr uint32_t ND = 1u << DB;
+  static_assert(BLK % (64 * kRadixR) == 0, "block is whole rounds");
   __shared__ uint32_t h[ND];
   for (uint32_t i = threadIdx.x; i < ND; i += 64) h[i] = 0;
   __syncthreads();
   const uint64_t base = (uint64_t)blockIdx.x * BLK;
-  for (int j = 0; j < BLK; j += 64) {
-    const uint64_t i = base + j + threadIdx.x;
-    if (i < n) atomicAdd(&h[(in[i] >> shift) & (ND - 1u)], 1u);
+  for (int j = 0; j < BLK; j += 64 * kRadixR) {
+    uint64_t rec[kRadixR];
+#pragma unroll
+    for (int u = 0; u < kRadixR; ++u) {
+      const uint64_t i = base + j + u * 64 + threadIdx.x;
+      rec[u] = i < n ? in[i] : ~0ull;
+    }
+#pragma unroll
+    for (int u = 0; u < kRadixR; ++u)
+      if (rec[u] != ~0ull) atomicAdd(&h[(rec[u] >> shift) & (ND - 1u)], 1u);
   }
   __syncthreads();
   for (uint32_t d = threadIdx.x; d < ND; d += 64) ghist[(uint64_t)d * nblk + blockIdx.x] = h[d];
 }
 
-template <int DB, int BLK>
+// STRIP: the pass is the last one, and writes each record's position only
+// (the final positions array) instead of the record.
+template <int DB, int BLK, bool STRIP>
 __global__ __launch_bounds__(64) void radix_scatter(const uint64_t *in, uint64_t n, uint32_t shift,
                                                     const uint64_t *goff, uint64_t nblk, uint64_t *out) {
   constexpr uint32_t ND = 1u << DB;
@@ -154,28 +167,44 @@ __global__ __launch_bounds__(64) void radix_scatter(const uint64_t *in, uint64_t
   const uint32_t lane = threadIdx.x;
   const uint64_t lt_mask = (1ull << lane) - 1ull;
   const uint64_t base = (uint64_t)blockIdx.x * BLK;
-  for (int j = 0; j < BLK; j += 64) {
-    const uint64_t i = base + j + lane;
-    const bool valid = i < n;
-    const uint64_t rec = valid ? in[i] : 0;
-    const uint32_t dg = (uint32_t)(rec >> shift) & (ND - 1u);
-    // lanes holding the same digit
-    uint64_t peers = ballot(valid);
+  for (int j = 0; j < BLK; j += 64 * kRadixR) {
+    uint64_t recs[kRadixR];
 #pragma unroll
-    for (int bit = 0; bit < DB; ++bit) {
-      const uint64_t ones = ballot(valid && ((dg >> bit) & 1u));
-      peers &= ((dg >> bit) & 1u) ? ones : ~ones;
+    for (int u = 0; u < kRadixR; ++u) {
+      const uint64_t i = base + j + u * 64 + lane;
+      recs[u] = i < n ? in[i] : ~0ull;
     }
-    const uint32_t rank = __builtin_popcountll(peers & lt_mask);
-    const uint64_t dst = run[dg] + rank;
-    __syncthreads();
-    if (valid) {
-      out[dst] = rec;
-      // the highest lane of each digit group advances the cursor
-      if ((peers >> lane) == 1ull) run[dg] += __builtin_popcountll(peers);
+#pragma unroll
+    for (int u = 0; u < kRadixR; ++u) {
+      const uint64_t rec = recs[u];
+      const bool valid = rec != ~0ull;
+      const uint32_t dg = (uint32_t)(rec >> shift) & (ND - 1u);
+      // lanes holding the same digit
+      uint64_t peers = ballot(valid);
+#pragma unroll
+      for (int bit = 0; bit < DB; ++bit) {
+        const uint64_t ones = ballot(valid && ((dg >> bit) & 1u));
+        peers &= ((dg >> bit) & 1u) ? ones : ~ones;
+      }
+      const uint32_t rank = __builtin_popcountll(peers & lt_mask);
+      const uint64_t dst = run[dg] + rank;
+      __syncthreads();
+      if (valid) {
+        out[dst] = STRIP ? (rec & kPosMask) : rec;
+        // the highest lane of each digit group advances the cursor
+        if ((peers >> lane) == 1ull) run[dg] += __builtin_popcountll(peers);
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
+}
+
+// offsets[j] = start of pid j = the scanned histogram at (digit j, block 0),
+// for a sort that took one pass over the whole pid; offsets[k] = n.
+__global__ void offsets_from_digits(const uint64_t *goff, uint64_t nblk, uint32_t k, uint64_t n, uint64_t *offsets) {
+  const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j > k) return;
+  offsets[j] = j < k ? goff[j * nblk] : n;
 }
 
 // offsets[j] = first index of pid j in the sorted records; offsets[k] = n.
@@ -237,7 +266,7 @@ uint32_t scan_lds_bytes(int cfg, uint32_t img_cap) {
   const TileCfg c = kTileCfgs[cfg];
   const uint32_t W = c.wg * c.c;
   const uint32_t tile = (kFront + W + 16 + 15) & ~15u;
-  return 2 * tile + kCandCap * 4 + 64 * 4 + img_cap;  // two tile slots
+  return 2 * tile + kCandCap * 2 + 64 * 4 + img_cap;  // two tile slots
 }
 
 // exclusive scan of n u32 counts into u64 offsets; tmp holds scan_tmp_words(n)
@@ -263,40 +292,56 @@ hipError_t launch_compact(const uint32_t *counts, const uint64_t *offs, uint64_t
 
 uint64_t radix_blocks(uint64_t n) { return (n + kRadixBlock - 1) / kRadixBlock; }
 
-// Stable sort of n records by pid (bits 40.. of each record) for pids below
-// 2^pid_bits: one 11-bit pass when 8 < pid_bits <= 11, else 8-bit passes.
-// Ping-pongs between a and b; returns the buffer holding the result.  ghist /
-// goff / tmp are sized for 256 * radix_blocks(n) entries, which also covers
-// the 11-bit pass (2048 digits per 8192-record block).
-hipError_t launch_radix(uint64_t *a, uint64_t *b, uint64_t n, uint32_t pid_bits, uint32_t *ghist, uint64_t *goff,
-                        uint64_t *tmp, uint64_t **result, hipStream_t s) {
+template <int DB>
+static hipError_t radix_one_pass(const uint64_t *src, uint64_t n, uint32_t k, uint32_t *ghist, uint64_t *goff,
+                                 uint64_t *tmp, uint64_t *offsets, uint64_t *positions, hipStream_t s) {
+  constexpr int BLK = DB == 8 ? kRadixBlock : kRadixBlock11;
+  const uint64_t nblk = (n + BLK - 1) / BLK;
+  hipLaunchKernelGGL((radix_hist<DB, BLK>), dim3((uint32_t)nblk), dim3(64), 0, s, src, n, kPosBits, ghist, nblk);
+  hipError_t e = launch_exclusive_scan(ghist, (1ull << DB) * nblk, goff, tmp, nullptr, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((radix_scatter<DB, BLK, true>), dim3((uint32_t)nblk), dim3(64), 0, s, src, n, kPosBits, goff,
+                     nblk, positions);
+  const uint64_t th = (uint64_t)k + 1;
+  hipLaunchKernelGGL(offsets_from_digits, dim3((uint32_t)((th + 255) / 256)), dim3(256), 0, s, goff, nblk, k, n,
+                     offsets);
+  return hipGetLastError();
+}
+
+// Stable sort of n records by pid (bits 40.. of each record, pids below k),
+// written out as per-pid offsets (k+1) and positions (n).  Up to 2,048 pids:
+// one pass whose digit is the whole pid, scattering positions straight to
+// their final place, with the offsets read from the scanned histogram.
+// Beyond: 8-bit passes ping-ponging between a and b, then a binary search
+// for the offsets and a strip of the records.  ghist / goff / tmp are sized
+// for 256 * radix_blocks(n) entries, which also covers the one-pass digits
+// (at most 2048 per 8192-record block).
+hipError_t launch_radix(uint64_t *a, uint64_t *b, uint64_t n, uint32_t k, uint32_t *ghist, uint64_t *goff,
+                        uint64_t *tmp, uint64_t *offsets, uint64_t *positions, hipStream_t s) {
+  uint32_t pid_bits = 0;
+  while (pid_bits < 32 && (1ull << pid_bits) < k) ++pid_bits;
+  if (n == 0) return hipSuccess;
+  if (pid_bits <= 8) return radix_one_pass<8>(a, n, k, ghist, goff, tmp, offsets, positions, s);
+  if (pid_bits == 9) return radix_one_pass<9>(a, n, k, ghist, goff, tmp, offsets, positions, s);
+  if (pid_bits == 10) return radix_one_pass<10>(a, n, k, ghist, goff, tmp, offsets, positions, s);
+  if (pid_bits == 11) return radix_one_pass<11>(a, n, k, ghist, goff, tmp, offsets, positions, s);
   uint64_t *src = a, *dst = b;
-  if (n > 0 && pid_bits > 8 && pid_bits <= 11) {
-    const uint64_t nblk = (n + kRadixBlock11 - 1) / kRadixBlock11;
-    hipLaunchKernelGGL((radix_hist<11, kRadixBlock11>), dim3((uint32_t)nblk), dim3(64), 0, s, src, n, kPosBits, ghist,
-                       nblk);
-    hipError_t e = launch_exclusive_scan(ghist, 2048 * nblk, goff, tmp, nullptr, s);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((radix_scatter<11, kRadixBlock11>), dim3((uint32_t)nblk), dim3(64), 0, s, src, n, kPosBits,
-                       goff, nblk, dst);
-    *result = dst;
-    return hipGetLastError();
-  }
   const uint64_t nblk = radix_blocks(n);
   const uint32_t npass = (pid_bits + 7) / 8;
-  for (uint32_t ps = 0; ps < npass && n > 0; ++ps) {
+  for (uint32_t ps = 0; ps < npass; ++ps) {
     const uint32_t shift = kPosBits + 8 * ps;
     hipLaunchKernelGGL((radix_hist<8, kRadixBlock>), dim3((uint32_t)nblk), dim3(64), 0, s, src, n, shift, ghist, nblk);
     hipError_t e = launch_exclusive_scan(ghist, 256 * nblk, goff, tmp, nullptr, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((radix_scatter<8, kRadixBlock>), dim3((uint32_t)nblk), dim3(64), 0, s, src, n, shift, goff,
-                       nblk, dst);
+    hipLaunchKernelGGL((radix_scatter<8, kRadixBlock, false>), dim3((uint32_t)nblk), dim3(64), 0, s, src, n, shift,
+                       goff, nblk, dst);
     uint64_t *t = src;
     src = dst;
     dst = t;
   }
-  *result = src;
-  return hipGetLastError();
+  hipError_t e = launch_pid_offsets(src, n, k, offsets, s);
+  if (e != hipSuccess) return e;
+  return launch_strip(src, n, positions, s);
 }
 
 hipError_t launch_pid_offsets(const uint64_t *sorted, uint64_t n, uint32_t k, uint64_t *offsets, hipStream_t s) {

@@ -286,7 +286,10 @@ struct WorkLayout {
   uint64_t nblk = 0, a = 0, b = 0, ghist = 0, goff = 0, tmp = 0, total = 0;
 };
 
-static WorkLayout work_layout(uint64_t total) {
+// work of a k-pattern collect: the compacted records (a), the ping-pong
+// buffer of the 8-bit passes (b, only beyond 2,048 patterns), the digit
+// histograms and their scan
+static WorkLayout work_layout(uint64_t total, uint32_t k) {
   WorkLayout w;
   w.nblk = radix_blocks(total);
   uint64_t o = 0;
@@ -295,11 +298,11 @@ static WorkLayout work_layout(uint64_t total) {
     o = align_up(o + bytes, 256);
     return r;
   };
-  // digit histograms: 256 per 1024-record block (8-bit passes) or 2048 per
-  // 8192-record block (one 11-bit pass), whichever is larger
+  // digit histograms: 256 per 1024-record block (8-bit passes) or up to 2048
+  // per 8192-record block (one pass of 9..11 bits), whichever is larger
   const uint64_t nh = std::max<uint64_t>(256 * w.nblk, 2048 * ((total + 8191) / 8192));
   w.a = take(total * 8);
-  w.b = take(total * 8);
+  w.b = k > 2048 ? take(total * 8) : w.a;
   w.ghist = take(nh * 4);
   w.goff = take(nh * 8);
   w.tmp = take(scan_tmp_words(nh) * 8);
@@ -309,14 +312,7 @@ static WorkLayout work_layout(uint64_t total) {
 
 uint64_t work_bytes_for(const rk_plan *plan, uint64_t total) {
   if (plan->k_total <= 1) return 0;
-  return work_layout(total).total;
-}
-
-// bits of the largest pattern id of k patterns (ids 0..k-1)
-static uint32_t pid_bits(uint32_t k) {
-  uint32_t b = 0;
-  while (b < 32 && (1ull << b) < k) ++b;
-  return b;
+  return work_layout(total, plan->k_total).total;
 }
 
 hipError_t prof_begin(rk_ctx *ctx, hipStream_t s, int kind, int *slot) {
@@ -556,7 +552,7 @@ rk_status collect_enqueue_known(rk_ctx *ctx, const rk_plan *plan, uint64_t n, vo
   uint64_t *tile_off = (uint64_t *)(sc + L.offsets);
   e = launch_exclusive_scan((const uint32_t *)(sc + L.counts), L.T, tile_off, (uint64_t *)(sc + L.tmp), nullptr, s);
   if (e != hipSuccess) return hip_err(ctx, e, "tile scan");
-  WorkLayout WL = work_layout(total);
+  WorkLayout WL = work_layout(total, k);
   uint64_t *target = k == 1 ? positions : (uint64_t *)((uint8_t *)work + WL.a);
   for (const PartRun &r : L.parts) {
     e = launch_compact((const uint32_t *)(sc + L.counts) + r.tile0, tile_off + r.tile0, r.ntiles,
@@ -598,14 +594,9 @@ rk_status collect_enqueue_known(rk_ctx *ctx, const rk_plan *plan, uint64_t n, vo
     if (e != hipSuccess) return hip_err(ctx, e, "offsets");
   } else {
     uint8_t *wk = (uint8_t *)work;
-    uint64_t *res = nullptr;
-    e = launch_radix((uint64_t *)(wk + WL.a), (uint64_t *)(wk + WL.b), total, pid_bits(k), (uint32_t *)(wk + WL.ghist),
-                     (uint64_t *)(wk + WL.goff), (uint64_t *)(wk + WL.tmp), &res, s);
+    e = launch_radix((uint64_t *)(wk + WL.a), (uint64_t *)(wk + WL.b), total, k, (uint32_t *)(wk + WL.ghist),
+                     (uint64_t *)(wk + WL.goff), (uint64_t *)(wk + WL.tmp), offsets, positions, s);
     if (e != hipSuccess) return hip_err(ctx, e, "radix sort");
-    e = launch_pid_offsets(res, total, k, offsets, s);
-    if (e != hipSuccess) return hip_err(ctx, e, "offsets");
-    e = launch_strip(res, total, positions, s);
-    if (e != hipSuccess) return hip_err(ctx, e, "strip");
   }
   e = prof_end(ctx, s, slot);
   if (e != hipSuccess) return hip_err(ctx, e, "profiling event");

@@ -91,8 +91,8 @@ static inline uint32_t next_pow2(uint32_t v) {
 // bytes older than that have shifted out of the 32-bit word.  So every pattern
 // of length >= 16 shares one hash stream (its key is the shift-add hash of
 // its last 16 bytes), likewise 8..15 and 4..7; lengths 1..3 get one group each
-// (the hash is masked to the window).  Exact mode needs one rolling stream per
-// length, so it groups by length.
+// (the hash is masked to the window).  Exact mode groups by length class, each
+// class keyed on the exact hash of the last l bytes, l its shortest length.
 struct PatRef {
   uint32_t pid;
   const uint8_t *p;
@@ -110,12 +110,17 @@ struct GroupIn {
 
 static uint32_t screen_mask(uint32_t m) { return (screen_shift(m) == 8 && m < 4) ? (1u << (8 * m)) - 1u : 0xFFFFFFFFu; }
 
-// group id for a pattern length under a mode: exact mode has one stream per
-// length up to kStreamM, and every longer pattern joins the kStreamM stream
-// (keyed by the hash of its last kStreamM bytes)
+// group id for a pattern length under a mode.  Lengths 1..3 get one group
+// each.  Screen mode: one group per shift (the span its hash covers).  Exact
+// mode: one group per length class (4..7, 8..15, 16..31, 32 and longer), whose
+// rolling stream hashes the last l bytes of each window, l the shortest
+// pattern length of the class (at most kStreamM): every pattern of the class
+// is keyed by the exact hash of its last l bytes, so a set of many lengths
+// costs one stream per class instead of one per length, and a class holding
+// one length hashes whole windows.
 static uint32_t group_id(int mode, uint32_t m) {
-  if (mode == RK_MODE_EXACT) return std::min(m, kStreamM);
   if (m < 4) return m;
+  if (mode == RK_MODE_EXACT) return 200 + (uint32_t)m_class(m);
   return 100 + screen_shift(m);
 }
 
@@ -266,6 +271,7 @@ static bool emit_group(const GroupIn &G, GroupBody &out) {
     max_m = std::max(max_m, P[i].m);
   }
   if (pb.size() > kGroupPatBytes) return false;  // split: entries address 4 MiB of pattern bytes
+  pb.resize(pb.size() + 16, 0);  // the kernel reads a pattern's first 16 bytes at once, whatever its length
   if (table) {
     // one record per cuckoo slot: the run of entries whose table key sits in
     // that slot, a single entry held inline
@@ -421,8 +427,8 @@ static std::vector<GroupIn> group_patterns(const uint8_t *bytes, const uint64_t 
     r.p = p;
     r.m = m;
     r.hx = host_hash(p, m);
-    // the window a group's stream hashes: the whole pattern, or its last
-    // kStreamM bytes in exact mode
+    // the window a group's stream hashes: the shortest length of the group,
+    // at most kStreamM bytes in exact mode
     const uint32_t ms = mode == RK_MODE_EXACT ? std::min(m, kStreamM) : m;
     if (G.pats.empty()) {
       G.screen = mode != RK_MODE_EXACT;
@@ -431,11 +437,18 @@ static std::vector<GroupIn> group_patterns(const uint8_t *bytes, const uint64_t 
       G.m = ms;
     }
     G.m = std::min(G.m, ms);
-    r.key = G.screen ? (uint64_t)screen_hash(p, m) : (m > kStreamM ? host_hash(p + m - kStreamM, kStreamM) : r.hx);
+    r.key = G.screen ? (uint64_t)screen_hash(p, m) : 0;
     G.pats.push_back(r);
   }
   std::vector<GroupIn> out;
-  for (auto &kv : by) out.push_back(kv.second);
+  for (auto &kv : by) {
+    GroupIn &G = kv.second;
+    // exact keys: the exact hash of each pattern's last G.m bytes (the whole
+    // pattern when it is that long)
+    if (!G.screen)
+      for (PatRef &r : G.pats) r.key = r.m == G.m ? r.hx : host_hash(r.p + r.m - G.m, G.m);
+    out.push_back(G);
+  }
   return out;
 }
 

@@ -15,7 +15,7 @@ constexpr uint32_t kStreamM = 64;          // longest window hashed by a rolling
                                            // keyed by their last kStreamM bytes
 constexpr uint32_t kPosBits = 40;          // hit record = pid << 40 | start position
 constexpr uint64_t kPosMask = (1ull << kPosBits) - 1;
-constexpr uint32_t kCandCap = 512;         // candidate slots in LDS per workgroup
+constexpr uint32_t kCandCap = 1024;        // candidate slots in LDS per workgroup (window index in the tile, u16)
 constexpr uint32_t kMaxWaves = 16;
 constexpr uint32_t kNoLink = 0xFFFFFFFFu;
 constexpr uint64_t kEmptyKey = ~0ull;      // empty exact-table slot (no canonical hash is >= q)
@@ -30,10 +30,10 @@ enum BucketKind : uint32_t {
 };
 
 // Group descriptor as laid out in an instance image (64 bytes).  A group is a
-// set of patterns tested with one hash stream: one length in exact mode, one
-// screen-hash span in screen mode.
+// set of patterns tested with one hash stream: one length class in exact mode
+// (keyed on its shortest length), one screen-hash span in screen mode.
 struct BucketDesc {
-  uint32_t m;          // exact groups: the pattern length; screen groups: the shortest length
+  uint32_t m;          // the group's shortest length: the window its exact stream hashes
   uint32_t kind;       // BucketKind
   uint32_t shift;      // screen groups: shift s in bits 0-7, list target count (1 or 4) in bits 8-15
   uint32_t mask;       // screen-hash mask (all ones unless m < 4 with s = 8)

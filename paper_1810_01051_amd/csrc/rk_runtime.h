@@ -204,8 +204,8 @@ hipError_t launch_exclusive_scan(const uint32_t *in, uint64_t n, uint64_t *out, 
 hipError_t launch_compact(const uint32_t *counts, const uint64_t *offs, uint64_t ntiles, const uint64_t *slabs,
                           uint32_t slab_cap, uint64_t *out, hipStream_t s);
 uint64_t radix_blocks(uint64_t n);
-hipError_t launch_radix(uint64_t *a, uint64_t *b, uint64_t n, uint32_t pid_bits, uint32_t *ghist, uint64_t *goff,
-                        uint64_t *tmp, uint64_t **result, hipStream_t s);
+hipError_t launch_radix(uint64_t *a, uint64_t *b, uint64_t n, uint32_t k, uint32_t *ghist, uint64_t *goff,
+                        uint64_t *tmp, uint64_t *offsets, uint64_t *positions, hipStream_t s);
 hipError_t launch_pid_offsets(const uint64_t *sorted, uint64_t n, uint32_t k, uint64_t *offsets, hipStream_t s);
 hipError_t launch_strip(const uint64_t *rec, uint64_t n, uint64_t *pos, hipStream_t s);
 hipError_t launch_single_offsets(uint64_t *offsets, uint64_t total, hipStream_t s);

@@ -448,29 +448,48 @@ __device__ __forceinline__ uint64_t exact_init(const uint32_t *w, uint32_t m) {
   return s;
 }
 
-// One exact rolling step: H(e) = 256 H(e-1) + in - out * 2^r  (r = 8m mod 61).
-// s < 2^63 on input, s < 2^62 + 2^11 on output.
-__device__ __forceinline__ uint64_t exact_step(uint64_t s, uint32_t in, uint32_t out, uint32_t r) {
-  return mul256_lazy(s) + in + (kQ - rot61(out, r));
-}
-
-// The same step with the 32-bit halves spelled out and the outgoing term
-// specialised on where out * 2^r lands in the 61-bit word (r = 8m mod 61 is
-// fixed per group):  OUTK 0: bits r..r+7 in the low word (r <= 24),
-// 1: in the high word (32 <= r <= 53), 2: anywhere (general rotation).
+// One exact rolling step: H(e) = 256 H(e-1) + in - out * 2^r  (r = 8m mod 61),
+// with the 32-bit halves spelled out and the outgoing term specialised on
+// where out * 2^r lands in the 61-bit word (r = 8m mod 61 is fixed per group):
+// OUTK 0: bits r..r+7 in the low word (r <= 24), 1: in the high word
+// (32 <= r <= 53), 2: anywhere (general rotation).
 //   256 s mod q = ((s << 8) & q) + (s >> 53): the low byte of s << 8 is free
-//   for the entering byte; q - v = q ^ v for v <= q.
-// Bounds as exact_step: s < 2^63 in, s < 2^62 + 2^11 out.
+//   for the entering byte (byte k of the word inw, merged by one byte
+//   permute); q - v = q ^ v for v <= q.
+// The sum (256 s + in) + (q - out * 2^r) + (s >> 53) is two add-with-carry
+// pairs (OUTK 0, 1).  s < 2^63 in, s < 2^62 + 2^11 out.
 template <int OUTK>
-__device__ __forceinline__ uint64_t exact_step_k(uint64_t s, uint32_t in, uint32_t out, uint32_t r) {
+__device__ __forceinline__ uint64_t exact_step_k(uint64_t s, uint32_t inw, uint32_t k, uint32_t out, uint32_t r) {
   const uint32_t lo = (uint32_t)s, hi = (uint32_t)(s >> 32);
-  const uint32_t alo = (lo << 8) | in;
+  const uint32_t alo = __builtin_amdgcn_perm(lo, inw, 0x06050400u | k);  // (lo << 8) | byte k of inw
   const uint32_t ahi = __builtin_amdgcn_alignbit(hi, lo, 24) & 0x1FFFFFFFu;
-  uint64_t neg;
-  if (OUTK == 0) neg = (0x1FFFFFFFull << 32) | (uint64_t)(uint32_t)~(out << r);
-  else if (OUTK == 1) neg = ((uint64_t)(0x1FFFFFFFu ^ (out << (r - 32))) << 32) | 0xFFFFFFFFull;
-  else neg = kQ - rot61(out, r);
-  return ((((uint64_t)ahi << 32) | alo) + neg) + (hi >> 21);
+  const uint32_t f = hi >> 21;
+  if constexpr (OUTK == 2) {
+    const uint64_t neg = kQ - rot61(out, r);
+    return ((((uint64_t)ahi << 32) | alo) + neg) + f;
+  } else {
+    uint32_t x, h;
+    if constexpr (OUTK == 0) {
+      // (the high word of q comes in a VGPR: with the carry in VCC a literal
+      // would be a second constant-bus read)
+      __asm__("v_add_co_u32 %0, vcc, %2, %3\n\t"
+              "v_addc_co_u32 %1, vcc, %6, %4, vcc\n\t"
+              "v_add_co_u32 %0, vcc, %0, %5\n\t"
+              "v_addc_co_u32 %1, vcc, 0, %1, vcc"
+              : "=&v"(x), "=&v"(h)
+              : "v"(alo), "v"(~(out << r)), "v"(ahi), "v"(f), "v"(0x1FFFFFFFu)
+              : "vcc");
+    } else {
+      __asm__("v_add_co_u32 %0, vcc, -1, %2\n\t"
+              "v_addc_co_u32 %1, vcc, %3, %4, vcc\n\t"
+              "v_add_co_u32 %0, vcc, %0, %5\n\t"
+              "v_addc_co_u32 %1, vcc, 0, %1, vcc"
+              : "=&v"(x), "=&v"(h)
+              : "v"(alo), "v"(0x1FFFFFFFu ^ (out << (r - 32))), "v"(ahi), "v"(f)
+              : "vcc");
+    }
+    return ((uint64_t)h << 32) | x;
+  }
 }
 
 __device__ __forceinline__ int out_kind(uint32_t r) { return r <= 24 ? 0 : ((r >= 32 && r <= 53) ? 1 : 2); }
@@ -510,7 +529,7 @@ __device__ __forceinline__ void roll_exact(const uint32_t *w, const uint32_t *d,
       ow = __builtin_amdgcn_alignbyte(dhi, dlo, os.sh);
       dlo = dhi;
     }
-    s = exact_step_k<OUTK>(s, byte_at(w, 64 + i), (ow >> (8 * (i & 3))) & 0xFFu, r);
+    s = exact_step_k<OUTK>(s, w[(64 + i) >> 2], (uint32_t)(i & 3), (ow >> (8 * (i & 3))) & 0xFFu, r);
     visit(i, s);
   }
 }
@@ -681,13 +700,18 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *wsum, 
   return before + x - v;
 }
 
-// The four bytes ending at *last (LDS, any alignment) as a big-endian word:
-// (last[-3] << 24) | ... | last[0], from the two aligned dwords that hold them.
-__device__ __forceinline__ uint32_t word_ending_at(const uint8_t *last) {
+// The four bytes ending at *last (LDS, any alignment) in memory order (the
+// oldest in the low byte), from the two aligned dwords that hold them.
+__device__ __forceinline__ uint32_t raw_word_ending_at(const uint8_t *last) {
   const uint8_t *a = last - 3;
   const uint32_t mis = (uint32_t)(uintptr_t)a & 3u;
   const uint32_t *aw = (const uint32_t *)(a - mis);
-  return __builtin_bswap32(__builtin_amdgcn_alignbyte(aw[1], aw[0], mis));
+  return __builtin_amdgcn_alignbyte(aw[1], aw[0], mis);
+}
+
+// The same four bytes as a big-endian word: (last[-3] << 24) | ... | last[0].
+__device__ __forceinline__ uint32_t word_ending_at(const uint8_t *last) {
+  return __builtin_bswap32(raw_word_ending_at(last));
 }
 
 // Exact hash (canonical) of the m <= kStreamM bytes ending at *end (LDS):
@@ -705,16 +729,24 @@ __device__ __forceinline__ uint64_t exact_key(const uint8_t *end, uint32_t m) {
   return canon(s);
 }
 
+// Shift-add value of four window bytes rw (memory order: the oldest in the
+// low byte) with the oldest weighted 2^(3s), ..., the newest 1: one byte dot
+// product for s = 2, two for s = 4, the big-endian word for s = 8.
+__device__ __forceinline__ uint32_t screen_word(uint32_t rw, uint32_t shift) {
+  if (shift == 2) return __builtin_amdgcn_udot4(rw, 0x01041040u, 0u, false);
+  if (shift == 4)
+    return (__builtin_amdgcn_udot4(rw, 0x00000110u, 0u, false) << 8) + __builtin_amdgcn_udot4(rw, 0x01100000u, 0u, false);
+  return __builtin_bswap32(rw);
+}
+
 // Shift-add hash of the span = 32/s bytes ending at *end (the value the scan's
 // screen pass held for that window end), masked as the group's hash is.
-// Four bytes at a time: each big-endian word's bytes weigh 2^(3s), ..., 1.
+// Four bytes at a time: word j back from the end weighs 2^(4 s j).
 __device__ __forceinline__ uint32_t screen_key(const uint8_t *end, uint32_t shift, uint32_t mask) {
   const uint32_t span = 32u / shift, nw = span >> 2;
   uint32_t h = 0;
   for (uint32_t j = nw; j-- > 0;) {
-    const uint32_t w = word_ending_at(end - 4 * j);
-    const uint32_t v = ((w >> 24) << (3 * shift)) + (((w >> 16) & 0xFFu) << (2 * shift)) +
-                       (((w >> 8) & 0xFFu) << shift) + (w & 0xFFu);
+    const uint32_t v = screen_word(raw_word_ending_at(end - 4 * j), shift);
     h = j == nw - 1u ? v : (h << (4 * shift)) + v;  // (one word when shift = 8: no 32-bit shift)
   }
   return h & mask;
@@ -736,16 +768,16 @@ __device__ __forceinline__ uint64_t key_lookup(const uint8_t *gimg, const Bucket
 }
 
 // Record of the 32-bit key h of a table bucket: the cuckoo slot holding h
-// (LDS) indexes the per-slot records in device memory; 0 if h is no key.
-// Branch-free (both slots probed, the record of one of them loaded), so that
-// the lookups of several candidates overlap.
+// (LDS) indexes the per-slot records in device memory.  The load is issued
+// without waiting for it: found tells whether h is a key at all (the record
+// is then to be dropped), so that the lookups of several candidates overlap.
 __device__ __forceinline__ uint64_t table_record(const uint8_t *img, const uint8_t *gimg, const BucketDesc &D,
-                                                 uint32_t h) {
+                                                 uint32_t h, bool &found) {
   const uint32_t *tab = (const uint32_t *)(img + D.fp_off);
   const uint32_t s1 = ck_slot1(h, D.fp_mask), s2 = ck_slot2(h, D.fp_mask);
   const bool in1 = tab[s1] == h, in2 = tab[s2] == h;
-  const uint64_t rec = ((const uint64_t *)(gimg + D.ht_off))[in1 ? s1 : s2];
-  return (in1 || in2) ? rec : 0;
+  found = in1 || in2;
+  return ((const uint64_t *)(gimg + D.ht_off))[in1 ? s1 : s2];
 }
 
 // Compares the m bytes ending at *end (LDS tile, any alignment) with the
@@ -758,6 +790,38 @@ __device__ __forceinline__ bool window_equals(const uint8_t *end, const uint8_t 
   const uint32_t *pw = (const uint32_t *)pat;
   uint32_t lo = aw[0];
   for (uint32_t q = 0; 4 * q < m; ++q) {
+    const uint32_t hi = aw[q + 1];
+    const uint32_t rem = m - 4 * q;
+    const uint32_t keep = rem >= 4 ? 0xFFFFFFFFu : ((1u << (8 * rem)) - 1u);
+    if ((__builtin_amdgcn_alignbyte(hi, lo, mis) ^ pw[q]) & keep) return false;
+    lo = hi;
+  }
+  return true;
+}
+
+// Compares the m <= kFront bytes ending at *end (LDS tile) with a pattern
+// whose first 16 bytes are hd (already in registers) and whose bytes are at
+// pat (device memory, 4-byte aligned): the first min(m, 16) bytes against hd,
+// the rest, if they agree, four bytes per step against pat.
+__device__ __forceinline__ bool window_equals_head(const uint8_t *end, const uint32_t (&hd)[4], const uint8_t *pat,
+                                                   uint32_t m) {
+  const uint8_t *a = end - (m - 1);
+  const uint32_t mis = (uint32_t)(uintptr_t)a & 3u;
+  const uint32_t *aw = (const uint32_t *)(a - mis);
+  uint32_t lo = aw[0], diff = 0;
+#pragma unroll
+  for (uint32_t q = 0; q < 4; ++q) {
+    if (4 * q < m) {
+      const uint32_t hi = aw[q + 1];
+      const uint32_t rem = m - 4 * q;
+      const uint32_t keep = rem >= 4 ? 0xFFFFFFFFu : ((1u << (8 * rem)) - 1u);
+      diff |= (__builtin_amdgcn_alignbyte(hi, lo, mis) ^ hd[q]) & keep;
+      lo = hi;
+    }
+  }
+  if (diff) return false;
+  const uint32_t *pw = (const uint32_t *)pat;
+  for (uint32_t q = 4; 4 * q < m; ++q) {
     const uint32_t hi = aw[q + 1];
     const uint32_t rem = m - 4 * q;
     const uint32_t keep = rem >= 4 ? 0xFFFFFFFFu : ((1u << (8 * rem)) - 1u);
@@ -908,13 +972,14 @@ __device__ __forceinline__ void dma_tile(uint8_t *slot, const uint8_t *text, uin
 // device image gimg), byte comparison with every pattern of the record.  Hits
 // go to the tile's slab (up to cap records) in window order; tile_hits counts
 // them all.  ncand returns the number of candidates (block-uniform).
-template <int WG, int C, bool PAIR>
+template <int WG, int C, int Q>
 __device__ __forceinline__ void candidate_phase(Bits<C> &bits, const BucketDesc &D, const uint8_t *tile, int64_t tstart,
                                                 uint64_t n, int64_t e0, const uint8_t *img, const uint8_t *gimg,
-                                                uint32_t *cand,
+                                                uint16_t *cand,
                                                 uint32_t *misc, uint64_t *slab, uint32_t cap, uint32_t &tile_hits,
                                                 uint32_t &ncand, const uint8_t *gtext,
                                                 unsigned long long *pid_counts, uint64_t rec1 = 0) {
+  static_assert(WG * C <= 65536, "window indices of a tile fit the u16 candidate list");
   constexpr uint32_t W = WG * C;
   constexpr int NB = (C + 31) / 32;
   const uint32_t tid = threadIdx.x;
@@ -954,7 +1019,7 @@ __device__ __forceinline__ void candidate_phase(Bits<C> &bits, const BucketDesc 
           const uint32_t hb = 31u - __builtin_clz(bb);  // highest bit = earliest window
           const uint32_t i = 32u * j + (uint32_t)word_windows<C>(j) - 1u - hb;
           bb &= ~(1u << hb);
-          if (idx >= r0 && idx < r0 + kCandCap) cand[idx - r0] = tid * C + i;
+          if (idx >= r0 && idx < r0 + kCandCap) cand[idx - r0] = (uint16_t)(tid * C + i);
           ++idx;
         }
       }
@@ -963,64 +1028,97 @@ __device__ __forceinline__ void candidate_phase(Bits<C> &bits, const BucketDesc 
     const uint32_t nc = min(kCandCap, ncand - r0);
     const bool screen = D.kind == kListScreen || D.kind == kTableScreen;
     const bool table = D.kind == kTableScreen || D.kind == kTableExact;
-    // PAIR: two adjacent candidates per thread, both records looked up
-    // before either is verified, so that their loads overlap (the pair keeps
-    // the candidates' order in the block scan of hit counts); otherwise one
-    // candidate per thread (fewer registers: the exact family keeps its
-    // occupancy).
-    auto record_of = [&](uint32_t ci, const uint8_t *&end, int64_t &e) __attribute__((always_inline)) -> uint64_t {
+    // The record stored under a candidate's key; the load is left in flight
+    // (found: whether the key is in the bucket at all).
+    auto record_of = [&](uint32_t ci, const uint8_t *&end, int64_t &e, bool &found)
+        __attribute__((always_inline)) -> uint64_t {
       const uint32_t e_rel = cand[ci];
       end = tile + kFront + e_rel;
       e = tstart + (int64_t)e_rel;
+      found = true;
       if (rec1) return rec1;  // the bucket has one key: every candidate's record
       const uint64_t key = screen ? (uint64_t)screen_key(end, D.shift & 0xFFu, D.mask) : exact_key(end, m);
-      return table ? table_record(img, gimg, D, (uint32_t)key) : key_lookup(gimg, D, key);
+      return table ? table_record(img, gimg, D, (uint32_t)key, found) : key_lookup(gimg, D, key);
     };
-    if constexpr (PAIR) {
-      for (uint32_t i0 = 0; i0 < nc; i0 += 2 * WG) {
-        const uint32_t ca = i0 + 2 * tid, cb = ca + 1;
-        const bool va = ca < nc, vb = cb < nc;
-        const uint8_t *enda, *endb;
-        int64_t ea, eb;
-        // out-of-range lanes look up the last candidate and drop the result
-        uint64_t reca = record_of(va ? ca : nc - 1, enda, ea);
-        uint64_t recb = record_of(vb ? cb : nc - 1, endb, eb);
-        if (!va) reca = 0;
-        if (!vb) recb = 0;
-        uint32_t ma = 0, mb = 0;
-        const uint32_t nha = reca ? verify_run(gimg, D, reca, enda, ea, gtext, ma) : 0;
-        const uint32_t nhb = recb ? verify_run(gimg, D, recb, endb, eb, gtext, mb) : 0;
-        uint32_t nht;
-        const uint32_t hb = block_excl_scan<WG>(nha + nhb, misc, nht);
-        if (nha) {
-          uint32_t o = tile_hits + hb;
-          write_hits(gimg, D, reca, ma, enda, ea, gtext, slab, cap, o, pid_counts);
-        }
-        if (nhb) {
-          uint32_t o = tile_hits + hb + nha;
-          write_hits(gimg, D, recb, mb, endb, eb, gtext, slab, cap, o, pid_counts);
-        }
-        tile_hits += nht;
+    // Up to Q candidates per thread, q = ceil(left / WG) of them, contiguous
+    // (thread order is candidate order, so the block scan of hit counts keeps
+    // the window order).  Three steps, each issuing its loads for all of the
+    // thread's candidates before any is waited for: the records; the first 16
+    // bytes of the pattern of each record that holds one pattern; the byte
+    // comparisons (longer patterns and runs of patterns read the rest then).
+    // Waves holding no candidate skip the lookups.  Q is 1 in the exact
+    // family (fewer registers: it keeps its occupancy).
+    for (uint32_t i0 = 0; i0 < nc; i0 += Q * WG) {
+      const uint32_t left = nc - i0;
+      const uint32_t q = left >= Q * WG ? Q : (left + WG - 1) / WG;  // uniform, 1..Q
+      const uint32_t c0 = i0 + tid * q;
+      const bool wave_has = i0 + (tid & ~63u) * q < nc;               // uniform per wave
+      uint64_t rec[Q];
+      const uint8_t *end[Q];
+      int64_t e[Q];
+      uint32_t nh[Q], hm[Q];
+      bool fnd[Q];
+#pragma unroll
+      for (int j = 0; j < Q; ++j) {
+        rec[j] = 0;
+        end[j] = tile;
+        e[j] = 0;
+        nh[j] = 0;
+        hm[j] = 0;
+        fnd[j] = false;
       }
-    } else {
-      for (uint32_t i0 = 0; i0 < nc; i0 += WG) {
-        const uint32_t ci = i0 + tid;
-        const uint8_t *end = tile;
-        int64_t e = 0;
-        uint64_t rec = 0;
-        uint32_t nh = 0, hmask = 0;
-        if (ci < nc) {
-          rec = record_of(ci, end, e);
-          nh = verify_run(gimg, D, rec, end, e, gtext, hmask);
+      if (wave_has) {
+#pragma unroll
+        for (int j = 0; j < Q; ++j) {
+          if ((uint32_t)j < q) {
+            // out-of-range lanes look up the last candidate and drop the result
+            const bool v = c0 + j < nc;
+            rec[j] = record_of(v ? c0 + j : nc - 1, end[j], e[j], fnd[j]);
+            fnd[j] = fnd[j] && v;
+          }
         }
-        uint32_t nht;
-        const uint32_t hb = block_excl_scan<WG>(nh, misc, nht);
-        if (nh) {
-          uint32_t o = tile_hits + hb;
-          write_hits(gimg, D, rec, hmask, end, e, gtext, slab, cap, o, pid_counts);
+        uint32_t hd[Q][4];
+#pragma unroll
+        for (int j = 0; j < Q; ++j) {
+          if (!fnd[j]) rec[j] = 0;
+          hd[j][0] = hd[j][1] = hd[j][2] = hd[j][3] = 0;
+          if ((uint32_t)j < q && (rec[j] >> 63)) {
+            const uint32_t *pw = (const uint32_t *)(gimg + D.pat_off + om_off((uint32_t)rec[j]));
+            hd[j][0] = pw[0];
+            hd[j][1] = pw[1];
+            hd[j][2] = pw[2];
+            hd[j][3] = pw[3];
+          }
         }
-        tile_hits += nht;
+#pragma unroll
+        for (int j = 0; j < Q; ++j) {
+          if ((uint32_t)j >= q || !rec[j]) continue;
+          if (rec[j] >> 63) {
+            // one pattern: starts inside the text, bytes equal (Sec. 3.1)
+            const uint32_t om = (uint32_t)rec[j], mj = om_len(om);
+            const int64_t x = e[j] - (int64_t)mj + 1;
+            const uint8_t *pat = gimg + D.pat_off + om_off(om);
+            const bool ok = x >= 0 && (mj <= kFront ? window_equals_head(end[j], hd[j], pat, mj)
+                                                     : window_equals_global(gtext + x, pat, mj));
+            hm[j] = ok ? 1u : 0u;
+            nh[j] = hm[j];
+          } else {
+            nh[j] = verify_run(gimg, D, rec[j], end[j], e[j], gtext, hm[j]);
+          }
+        }
       }
+      uint32_t mine = 0;
+#pragma unroll
+      for (int j = 0; j < Q; ++j) mine += nh[j];
+      uint32_t nht;
+      const uint32_t hb = block_excl_scan<WG>(mine, misc, nht);
+      if (mine) {
+        uint32_t o = tile_hits + hb;
+#pragma unroll
+        for (int j = 0; j < Q; ++j)
+          if (nh[j]) write_hits(gimg, D, rec[j], hm[j], end[j], e[j], gtext, slab, cap, o, pid_counts);
+      }
+      tile_hits += nht;
     }
   }
 }
@@ -1054,15 +1152,15 @@ __device__ __forceinline__ BucketDesc read_desc(const uint8_t *img, uint32_t b) 
 
 // ------------------------------------------------------------ the scan kernel
 //
-// LDS: [slot 0][slot 1][cand: kCandCap u32][misc: 64 u32][image: img_cap]
+// LDS: [slot 0][slot 1][cand: kCandCap u16][misc: 64 u32][image: img_cap]
 template <int WG, int C, int FAM>
 __global__ __launch_bounds__(WG) void scan_kernel(ScanParams p) {
   constexpr uint32_t W = WG * C;
   constexpr uint32_t TILE_LDS = (kFront + W + 16 + 15) & ~15u;  // one slot
   constexpr int NB = (C + 31) / 32;
   extern __shared__ __align__(16) uint8_t lds[];
-  uint32_t *cand = (uint32_t *)(lds + 2 * TILE_LDS);
-  uint32_t *misc = cand + kCandCap;  // [0,16) scan sums, [16,48) any flags, [48] queue
+  uint16_t *cand = (uint16_t *)(lds + 2 * TILE_LDS);
+  uint32_t *misc = (uint32_t *)(cand + kCandCap);  // [0,16) scan sums, [16,48) any flags, [48] queue
   uint8_t *img = (uint8_t *)(misc + 64);
 
   const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -1207,7 +1305,8 @@ __global__ __launch_bounds__(WG) void scan_kernel(ScanParams p) {
         uint64_t dummy = 0;
         run_pass<C, false, FAM>(D, tw, os, r, (const uint32_t *)(img + D.fp_off), dummy, bits);
         uint32_t ncand;
-        candidate_phase<WG, C, FAM != kFamExact>(bits, D, tile, tstart, n, e0, img, gimg, cand, misc, slab, cap,
+        candidate_phase<WG, C, FAM == kFamExact ? 1 : kCandCap / WG>(bits, D, tile, tstart, n, e0, img, gimg, cand,
+                                                                     misc, slab, cap,
                                                      tile_hits, ncand,
                                cur.text, p.direct ? nullptr : p.pid_counts);
         if (b < 32) dense_mask = ncand >= kDenseCand ? (dense_mask | (1u << b)) : (dense_mask & ~(1u << b));
@@ -1242,15 +1341,15 @@ __global__ __launch_bounds__(WG) void scan_kernel(ScanParams p) {
 // so that it does not wait for the new loads), then tile t+1's loads are
 // issued, then the test runs on registers only.
 //
-// LDS: [slot 0][slot 1][cand: kCandCap u32][misc: 64 u32]
+// LDS: [slot 0][slot 1][cand: kCandCap u16][misc: 64 u32]
 template <int WG, int C, int FAM>
 __global__ __launch_bounds__(WG) void scan_list_kernel(ListParams p) {
   constexpr uint32_t W = WG * C;
   constexpr uint32_t TILE_LDS = (kFront + W + 16 + 15) & ~15u;
   constexpr int NB = (C + 31) / 32;
   extern __shared__ __align__(16) uint8_t lds[];
-  uint32_t *cand = (uint32_t *)(lds + 2 * TILE_LDS);
-  uint32_t *misc = cand + kCandCap;
+  uint16_t *cand = (uint16_t *)(lds + 2 * TILE_LDS);
+  uint32_t *misc = (uint32_t *)(cand + kCandCap);
   const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const BucketDesc D = p.D;
   const uint32_t m = D.m;
@@ -1302,7 +1401,7 @@ __global__ __launch_bounds__(WG) void scan_list_kernel(ListParams p) {
       uint64_t dummy = 0;
       run_pass<C, false, FAM, true>(D, tw, os, r, nullptr, dummy, bits, &pre);
       uint32_t ncand;
-      candidate_phase<WG, C, FAM != kFamExact>(bits, D, tile, tstart, p.n, e0, nullptr, p.gimg, cand, misc,
+      candidate_phase<WG, C, FAM == kFamExact ? 1 : 2>(bits, D, tile, tstart, p.n, e0, nullptr, p.gimg, cand, misc,
                              p.out + t * (uint64_t)p.slab_cap, p.slab_cap, tile_hits, ncand, p.text, p.pid_counts,
                              p.rec1);
       dense = ncand >= kDenseCand;
@@ -1323,7 +1422,7 @@ __global__ __launch_bounds__(WG) void scan_list_kernel(ListParams p) {
 // ------------------------------------------------------------------ launchers
 template <int WG, int C>
 constexpr uint32_t list_lds_bytes_t() {
-  return 2 * ((kFront + WG * C + 16 + 15) & ~15u) + kCandCap * 4 + 64 * 4;
+  return 2 * ((kFront + WG * C + 16 + 15) & ~15u) + kCandCap * 2 + 64 * 4;
 }
 
 template <int WG, int C, int FAM>

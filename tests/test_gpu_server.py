@@ -233,7 +233,11 @@ def test_admission_wait_is_bounded(ctx, rk, corpora):
     pats = [h[o:o + m].tobytes() for o, m in ((10, 1), (2000, 1), (40000, 2))]
     ref = oracle.search(h, pats)
     hits = int(ref[0][-1])
-    srv = rk.Server(ctx, arena_bytes=48 * hits, max_inflight=1, max_step_requests=1, admission_timeout_s=0.2)
+    # a step needs about 19 bytes per hit of the arena (8 for the positions,
+    # 8 for the records being sorted, the digit histograms); a finished,
+    # unreleased result keeps its 8: 32 bytes per hit admit two steps and
+    # leave the third without room
+    srv = rk.Server(ctx, arena_bytes=32 * hits, max_inflight=1, max_step_requests=1, admission_timeout_s=0.2)
     srv.add_corpus(text)
     t0 = time.perf_counter()
     rids = [srv.submit(0, pats) for _ in range(4)]
