@@ -313,9 +313,10 @@ typedef struct {
 /* Plan for `count` independent searches (each the problem of Sec. 1 on its
  * own text; the paper runs one search per launch, Sec. 3.1) scanned by
  * persistent launches (one per scan geometry in use), each over an atomic
- * work queue of (instance, pattern-length bucket, tile) items ordered by
- * bucket; each bucket's geometry comes from the autotuner's table
- * (rk_autotune / rk_autotune_load).  Instance i's
+ * work queue of (instance, tile) items.  Each instance's text is scanned once
+ * for all its pattern-length buckets, with the geometry whose tuned bucket
+ * timings (rk_autotune / rk_autotune_load) sum to the least over the
+ * instance's buckets.  Instance i's
  * patterns get global ids base_i + j with base_i = sum of k over instances
  * before i.  The plan keeps the text pointers; the texts must stay alive and
  * unchanged while the plan is used. */
@@ -340,8 +341,9 @@ uint64_t rk_plan_text_bytes(const rk_plan *plan);
  *     (n_b = min(n, 1 MiB) for m-class 0, min(n, 32 MiB) otherwise), pattern j
  *     of length lo + j mod (hi - lo + 1) copied from the text at
  *     (n_b/3 + 7919 j) mod (n_b - m + 1), reversed when j is odd,
- * stores the fastest geometry of each in the context (batch plans take each
- * m-bucket image's geometry from the bucket table) and, if path is non-NULL,
+ * stores the fastest geometry of each and every bucket timing in the context
+ * (a batch instance is scanned once, all its m-buckets together, with the
+ * geometry of least tuned time summed over its buckets) and, if path is non-NULL,
  * writes the table as JSON with every candidate's time, hit count and digest
  * of its result (sum of v[i] * (2i + 1) mod 2^64 over the offsets followed by
  * the positions).  Every candidate must return the same hits (RK_EDEVICE otherwise).

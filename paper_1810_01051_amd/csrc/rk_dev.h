@@ -42,4 +42,5 @@ __device__ __forceinline__ void wg_barrier_loads() {
   __asm__ volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
+
 }  // namespace rk

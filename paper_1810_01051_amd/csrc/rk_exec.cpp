@@ -16,7 +16,7 @@ namespace rk {
 
 // images are built per real instance (defined in rk_host.cpp)
 rk_status build_instance_images(rk_ctx *ctx, const uint8_t *bytes, const uint64_t *offs, uint32_t k,
-                                uint32_t pid_base, int mode, uint32_t src, bool by_class, std::vector<VInst> &vinsts,
+                                uint32_t pid_base, int mode, uint32_t src, std::vector<VInst> &vinsts,
                                 std::vector<uint8_t> &blob);
 
 static inline uint64_t align_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
@@ -28,14 +28,35 @@ static int pick_cfg(const rk_ctx *ctx, int mode, uint32_t m) {
   return 0;
 }
 
-// Geometry of one m-bucket image of a batch: the tuned choice for its
-// (mode, m-class, pattern-count class), else the single-pattern choice for
-// its longest stream.
-static int pick_bucket_cfg(const rk_ctx *ctx, int mode, const VInst &v) {
+// Scan geometry of a batch instance: the one with the least tuned time per
+// MiB summed over the instance's m-buckets (each bucket timed alone by the
+// autotuner; the instance's buckets share one scan of its text), else the
+// tuned choice of its largest bucket, else the per-length choice.
+static int instance_cfg(const rk_ctx *ctx, int mode, const uint32_t npat[kNumMClass], uint32_t max_m) {
   if (ctx->tile_cfg >= 0) return ctx->tile_cfg;
   const int md = mode == RK_MODE_EXACT ? 1 : 2;
-  if (v.mclass >= 0 && ctx->tune_b[md][v.mclass][k_class(v.npat)] >= 0) return ctx->tune_b[md][v.mclass][k_class(v.npat)];
-  return pick_cfg(ctx, mode, std::min(v.max_m, kStreamM));
+  int best = -1;
+  double best_ms = 0;
+  for (int g = 0; g < kNumTileCfg; ++g) {
+    double sum = 0;
+    bool known = true;
+    for (int c = 0; c < kNumMClass && known; ++c) {
+      if (!npat[c]) continue;
+      const double t = ctx->tune_bms[md][c][k_class(npat[c])][g];
+      known = t >= 0;
+      sum += t;
+    }
+    if (known && (best < 0 || sum < best_ms)) {
+      best = g;
+      best_ms = sum;
+    }
+  }
+  if (best >= 0) return best;
+  int cmax = 0;
+  for (int c = 1; c < kNumMClass; ++c)
+    if (npat[c] > npat[cmax]) cmax = c;
+  if (npat[cmax] && ctx->tune_b[md][cmax][k_class(npat[cmax])] >= 0) return ctx->tune_b[md][cmax][k_class(npat[cmax])];
+  return pick_cfg(ctx, mode, std::min(std::max(max_m, 1u), kStreamM));
 }
 
 static int part_family(int mode, const std::vector<VInst> &vs, const std::vector<uint32_t> &members) {
@@ -75,13 +96,22 @@ rk_status plan_build_host(rk_ctx *ctx, const rk_instance *inst, uint32_t count, 
     R.pid_base = (uint32_t)ktot;
     R.k = I.k;
     P->insts.push_back(R);
-    rk_status st = build_instance_images(ctx, I.bytes_host, I.offsets_host, I.k, (uint32_t)ktot, mode, i, batch,
+    const size_t v0 = P->vinsts.size();
+    rk_status st = build_instance_images(ctx, I.bytes_host, I.offsets_host, I.k, (uint32_t)ktot, mode, i,
                                          P->vinsts, blob);
     if (st != RK_OK) return st;
+    uint32_t inst_max_m = 0;
     for (uint32_t j = 0; j < I.k; ++j) {
       const uint32_t m = (uint32_t)(I.offsets_host[j + 1] - I.offsets_host[j]);
       mweight[m] += (double)(batch ? I.n : 1) + 1.0;
       P->max_m = std::max(P->max_m, m);
+      inst_max_m = std::max(inst_max_m, m);
+    }
+    if (batch) {
+      uint32_t npat[kNumMClass];
+      instance_buckets(I.bytes_host, I.offsets_host, I.k, mode, npat);
+      const int g = instance_cfg(ctx, mode, npat, inst_max_m);
+      for (size_t vi = v0; vi < P->vinsts.size(); ++vi) P->vinsts[vi].cfg = g;
     }
     ktot += I.k;
     P->text_bytes += batch ? I.n : 0;
@@ -128,17 +158,14 @@ rk_status plan_build_host(rk_ctx *ctx, const rk_instance *inst, uint32_t count, 
     P->parts.assign(1, pt);
     return RK_OK;
   }
-  // Batch: every (instance, m-bucket) image gets the geometry tuned for its
-  // bucket; the images of one geometry form a part, scanned by one
-  // persistent launch over a work queue of (instance, m-bucket, tile) items
-  // ordered by m-bucket (then heavier images first, then instance), so that a
-  // workgroup keeps one image across consecutive pops.
+  // Batch: every instance image holds all its m-buckets (one scan of its
+  // text) and takes the geometry its buckets' tuned timings favour; the
+  // images of one geometry form a part, scanned by one persistent launch over
+  // a work queue of (instance, tile) items, heavier images (more buckets,
+  // longer patterns) first, so that a workgroup keeps one image across
+  // consecutive pops.
   std::vector<uint32_t> members[kMaxParts];
-  for (uint32_t vi = 0; vi < P->vinsts.size(); ++vi) {
-    VInst &v = P->vinsts[vi];
-    v.cfg = pick_bucket_cfg(ctx, mode, v);
-    members[v.cfg].push_back(vi);
-  }
+  for (uint32_t vi = 0; vi < P->vinsts.size(); ++vi) members[P->vinsts[vi].cfg].push_back(vi);
   uint64_t base = 0;
   for (int c = 0; c < kNumTileCfg; ++c) {
     if (members[c].empty()) continue;
@@ -172,7 +199,6 @@ rk_status plan_build_host(rk_ctx *ctx, const rk_instance *inst, uint32_t count, 
     for (uint32_t q = 0; q < order.size(); ++q) order[q] = q;
     std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
       const VInst &x = P->vinsts[members[c][a]], &y = P->vinsts[members[c][b]];
-      if (x.mclass != y.mclass) return x.mclass < y.mclass;
       if (x.nbuckets != y.nbuckets) return x.nbuckets > y.nbuckets;
       return x.max_m > y.max_m;
     });

@@ -331,7 +331,7 @@ static void expand_group(const GroupIn &G, std::vector<GroupBody> &bodies) {
 // Packs groups greedily into virtual instances whose LDS part (header,
 // descriptors, cuckoo tables) fits kImgLimit.  Image layout:
 //   [ImageHeader][BucketDesc x nb][LDS parts ...][device-memory parts ...]
-static rk_status build_images(rk_ctx *ctx, const std::vector<GroupIn> &groups, int mclass, uint32_t src_inst,
+static rk_status build_images(rk_ctx *ctx, const std::vector<GroupIn> &groups, uint32_t src_inst,
                               std::vector<VInst> &vinsts, std::vector<uint8_t> &blob) {
   std::vector<GroupBody> bodies;
   for (const GroupIn &G : groups) expand_group(G, bodies);
@@ -391,7 +391,6 @@ static rk_status build_images(rk_ctx *ctx, const std::vector<GroupIn> &groups, i
     v.nbuckets = hd.nbuckets;
     v.max_m = max_m;
     v.npat = npat;
-    v.mclass = mclass;
     v.only_one_list = only_one_list;
     blob.resize(v.img_off, 0);
     blob.insert(blob.end(), img.begin(), img.end());
@@ -452,23 +451,21 @@ static std::vector<GroupIn> group_patterns(const uint8_t *bytes, const uint64_t 
   return out;
 }
 
-// Images of one instance's patterns.  by_class: one set of images per
-// m-bucket (the groups whose stream length falls in one m_class), so that a
-// batch's work queue holds (instance, m-bucket, tile) items; otherwise every
-// group of the instance shares its images (one scan of the text).
+// Images of one instance's patterns: every group of the instance shares its
+// images (one scan of the text).
 rk_status build_instance_images(rk_ctx *ctx, const uint8_t *bytes, const uint64_t *offs, uint32_t k,
-                                uint32_t pid_base, int mode, uint32_t src, bool by_class, std::vector<VInst> &vinsts,
+                                uint32_t pid_base, int mode, uint32_t src, std::vector<VInst> &vinsts,
                                 std::vector<uint8_t> &blob) {
   rk_status st = validate_patterns(ctx, bytes, offs, k);
   if (st != RK_OK) return st;
   if (k == 0) return RK_OK;  // nothing to scan for
-  std::vector<GroupIn> groups = group_patterns(bytes, offs, k, pid_base, mode);
-  if (!by_class) return build_images(ctx, groups, -1, src, vinsts, blob);
-  std::vector<GroupIn> cls[kNumMClass];
-  for (GroupIn &G : groups) cls[m_class(G.m)].push_back(std::move(G));
-  for (int c = 0; c < kNumMClass && st == RK_OK; ++c)
-    if (!cls[c].empty()) st = build_images(ctx, cls[c], c, src, vinsts, blob);
-  return st;
+  return build_images(ctx, group_patterns(bytes, offs, k, pid_base, mode), src, vinsts, blob);
+}
+
+void instance_buckets(const uint8_t *bytes, const uint64_t *offs, uint32_t k, int mode, uint32_t npat[kNumMClass]) {
+  for (int c = 0; c < kNumMClass; ++c) npat[c] = 0;
+  if (k == 0) return;
+  for (const GroupIn &G : group_patterns(bytes, offs, k, 0, mode)) npat[m_class(G.m)] += (uint32_t)G.pats.size();
 }
 
 }  // namespace rk
@@ -522,7 +519,10 @@ rk_status rk_ctx_create(int device, uint64_t d, uint64_t q, rk_ctx **out) {
   for (int md = 0; md < 3; ++md) {
     for (int m = 0; m <= RK_MAX_M; ++m) c->tune[md][m] = -1;
     for (int a = 0; a < kNumMClass; ++a)
-      for (int b = 0; b < kNumKClass; ++b) c->tune_b[md][a][b] = -1;
+      for (int b = 0; b < kNumKClass; ++b) {
+        c->tune_b[md][a][b] = -1;
+        for (int g = 0; g < kNumTileCfg; ++g) c->tune_bms[md][a][b][g] = -1.0;
+      }
   }
   prepare_scan_kernels();
   if (static_scratch_setup(c) != RK_OK) {

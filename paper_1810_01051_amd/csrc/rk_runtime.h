@@ -44,7 +44,6 @@ struct VInst {
   uint32_t nbuckets = 0;
   uint32_t max_m = 0;
   uint32_t npat = 0;   // patterns in the image
-  int mclass = -1;     // m-bucket of its groups (batch plans), -1: mixed
   int cfg = 0;         // scan geometry
   bool only_one_list = true;  // every bucket is a list screen with one target
 };
@@ -86,6 +85,8 @@ struct rk_ctx {
   int tune[3][RK_MAX_M + 1];
   uint8_t tune_measured[3][RK_MAX_M + 1] = {};
   int tune_b[3][rk::kNumMClass][rk::kNumKClass];  // batch buckets: geometry per (mode, m-class, k-class)
+  // batch buckets: tuned time per MiB of text for each geometry (< 0: not measured)
+  double tune_bms[3][rk::kNumMClass][rk::kNumKClass][rk::kNumTileCfg];
   rk::CountMemo memo[16];
   uint32_t memo_next = 0;
   void *dump_dev = nullptr;    // device copy of the dump image
@@ -213,6 +214,9 @@ hipError_t launch_window_hashes(const uint8_t *text, uint64_t n, uint32_t m, con
                                 uint64_t *out, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint64_t words, uint32_t v, hipStream_t s);
 rk_status tune_run(rk_ctx *ctx, uint64_t n, const uint32_t *lengths, uint32_t nl, const char *path);
+// patterns of an instance per m-bucket (the m-class of each group's stream
+// length) under a mode; npat[c] = 0 for an empty bucket
+void instance_buckets(const uint8_t *bytes, const uint64_t *offs, uint32_t k, int mode, uint32_t npat[kNumMClass]);
 rk_status tune_load(rk_ctx *ctx, const char *path);
 rk_status static_scratch_setup(rk_ctx *ctx);
 

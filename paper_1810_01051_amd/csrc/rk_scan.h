@@ -926,7 +926,19 @@ __device__ __forceinline__ void write_hits(const uint8_t *gimg, const BucketDesc
 }
 
 // ------------------------------------------------------- tile staging (LDS DMA)
-typedef __attribute__((address_space(3))) void lds_void_t;
+// One 16-byte chunk per active lane from device memory straight into LDS:
+// lane i's chunk at g lands at dst + 16 i (dst wave-uniform).  Issued in asm
+// so that the compiler does not see an LDS write in flight: it would make
+// every later LDS read wait for all such loads (vmcnt(0)), the reads of the
+// tile being tested included, so that the next tile's loads would no longer
+// overlap its test.  Every read of a slot is ordered after that slot's loads
+// by the tile pipeline's own waits (wg_barrier_loads).
+// (M0 holds the LDS address, placed there by the compiler; the s_nop is the
+// wait state required between a write of M0 and the load that uses it.)
+__device__ __forceinline__ void lds_dma16(const void *g, const uint8_t *dst) {
+  const uint32_t m0 = __builtin_amdgcn_readfirstlane(lds_addr(dst));
+  __asm__ volatile("s_nop 0\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(g), "{m0}"(m0) : "memory");
+}
 
 // Issues the loads of one tile into an LDS slot: text bytes [tstart - kFront,
 // tstart + W) as 16-byte chunks that the load unit writes straight into LDS
@@ -945,21 +957,20 @@ __device__ __forceinline__ void dma_tile(uint8_t *slot, const uint8_t *text, uin
     // interior tile: every chunk is text
     const uint8_t *base = text + tstart + 16u * lane;
     for (uint32_t j = wave; j < J; j += NW)
-      __builtin_amdgcn_global_load_lds((const void *)(base + 1024u * j), (lds_void_t *)(slot + kFront + 1024u * j), 16,
-                                       0, 0);
+      lds_dma16(base + 1024u * j, slot + kFront + 1024u * j);
     if (wave == NW - 1 && lane < 4)
-      __builtin_amdgcn_global_load_lds((const void *)(base - kFront), (lds_void_t *)slot, 16, 0, 0);
+      lds_dma16(base - kFront, slot);
     return;
   }
   for (uint32_t j = wave; j < J; j += NW) {
     const uint64_t g = (uint64_t)tstart + 1024u * j + 16u * lane;
     const uint8_t *src = g < n ? text + g : text;
-    __builtin_amdgcn_global_load_lds((const void *)src, (lds_void_t *)(slot + kFront + 1024u * j), 16, 0, 0);
+    lds_dma16(src, slot + kFront + 1024u * j);
   }
   if (wave == NW - 1 && lane < 4) {
     const int64_t g = tstart - (int64_t)kFront + 16 * (int64_t)lane;
     const uint8_t *src = g >= 0 ? text + g : text;
-    __builtin_amdgcn_global_load_lds((const void *)src, (lds_void_t *)slot, 16, 0, 0);
+    lds_dma16(src, slot);
   }
 }
 
@@ -1121,6 +1132,10 @@ __device__ __forceinline__ void candidate_phase(Bits<C> &bits, const BucketDesc 
       tile_hits += nht;
     }
   }
+  // nothing of this phase left in flight (a load whose value some path did
+  // not use would otherwise make the compiler wait for it, with a count that
+  // also covers the next tile's loads, at the next LDS read)
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
 }
 
 // A tile with at least this many candidates in a bucket makes the next tile

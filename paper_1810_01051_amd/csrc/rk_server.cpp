@@ -281,13 +281,13 @@ static rk_status start_step(rk_server *S, Slot &sl, std::unique_lock<std::mutex>
   std::vector<Request *> take;
   uint64_t pats = 0;
   // requests are also bounded by the output the step is expected to need:
-  // about 28 bytes per hit (positions, sort buffers, histograms) at the hit
+  // about 20 bytes per hit (positions, sort buffer, histograms) at the hit
   // rate per pattern seen so far must fit the slot's share of the arena; the
   // first step, with no estimate yet, takes a few requests only
   uint32_t limit = std::min(S->cfg.max_step_requests, std::max<uint32_t>(S->step_limit, 1));
   if (S->hits_per_pattern < 0) limit = std::min<uint32_t>(limit, 8);
   const double share = (double)S->arena.cap / (double)S->slots.size();
-  const double per_pat = S->hits_per_pattern < 0 ? 0.0 : 28.0 * S->hits_per_pattern;
+  const double per_pat = S->hits_per_pattern < 0 ? 0.0 : 20.0 * S->hits_per_pattern;
   // A step serves one corpus: the oldest waiting request's, with the other
   // waiting requests for that corpus in arrival order (requests for other
   // corpora keep their places).  One corpus per step lets its requests share

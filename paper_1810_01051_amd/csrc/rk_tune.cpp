@@ -252,6 +252,7 @@ rk_status tune_run(rk_ctx *ctx, uint64_t n, const uint32_t *lengths, uint32_t nl
                    (unsigned long long)o.digest);
           brows.push_back(row);
           cfg_ms[cfg] = o.ms;
+          ctx->tune_bms[md][mc][kc][cfg] = o.ms * (double)(1u << 20) / (double)nb;
         }
         ctx->tune_b[md][mc][kc] = pick_best(cfg_ms, kNumTileCfg);
       }
@@ -290,7 +291,8 @@ rk_status tune_run(rk_ctx *ctx, uint64_t n, const uint32_t *lengths, uint32_t nl
   return RK_OK;
 }
 
-// Minimal reader for the file written above: the arch string, the
+// Minimal reader for the file written above: the arch string, the bucket
+// timings (time per MiB of each geometry for each bucket shape), the
 // {"bmode": a, "mclass": b, "kclass": c, "cfg": d} objects after "buckets" and
 // the {"mode": a, "m": b, "cfg": c} objects after "choice".
 rk_status tune_load(rk_ctx *ctx, const char *path) {
@@ -314,6 +316,21 @@ rk_status tune_load(rk_ctx *ctx, const char *path) {
           md >= 1 && md <= 2 && mc >= 0 && mc < kNumMClass && kc >= 0 && kc < kNumKClass && cfg >= 0 &&
           cfg < kNumTileCfg)
         ctx->tune_b[md][mc][kc] = cfg;
+      ++p;
+    }
+  }
+  p = s.find("\"bucket_timings\"");
+  if (p != std::string::npos) {
+    const size_t stop = s.find("\"buckets\"", p);
+    unsigned kk;
+    unsigned long long nb;
+    double ms;
+    while ((p = s.find("{\"mode\": ", p)) != std::string::npos && p < stop) {
+      if (sscanf(s.c_str() + p, "{\"mode\": %d, \"mclass\": %d, \"kclass\": %d, \"k\": %u, \"n\": %llu, \"cfg\": %d, \"ms\": %lf",
+                 &md, &mc, &kc, &kk, &nb, &cfg, &ms) == 7 &&
+          md >= 1 && md <= 2 && mc >= 0 && mc < kNumMClass && kc >= 0 && kc < kNumKClass && cfg >= 0 &&
+          cfg < kNumTileCfg && nb > 0 && ms > 0)
+        ctx->tune_bms[md][mc][kc][cfg] = ms * (double)(1u << 20) / (double)nb;
       ++p;
     }
   }

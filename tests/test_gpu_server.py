@@ -131,7 +131,7 @@ def test_cancel_and_errors(ctx, rk, corpora):
 def test_oversized_steps_are_split(ctx, rk, corpora):
     """A step whose merged output does not fit the arena goes back to the
     queue and is split; every request still gets its exact result.  The arena
-    holds one request's output and sort work (about 27 bytes per hit) but not
+    holds one request's output and sort work (about 19 bytes per hit) but not
     two, so any step of two or more requests must be split."""
     text = corpora[2]
     h = text.cpu().numpy()
@@ -142,7 +142,7 @@ def test_oversized_steps_are_split(ctx, rk, corpora):
     ref = [oracle.search(h, r) for r in reqs]
     hits = int(ref[0][0][-1])
     assert hits > 20000
-    srv = rk.Server(ctx, arena_bytes=40 * hits, max_inflight=1, max_step_requests=64)
+    srv = rk.Server(ctx, arena_bytes=30 * hits, max_inflight=1, max_step_requests=64)
     srv.add_corpus(text)
     rids = [srv.submit(0, r) for r in reqs]
     # results are released as they are checked: unreleased results hold arena
