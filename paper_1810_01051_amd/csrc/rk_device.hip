@@ -129,7 +129,7 @@ __global__ __launch_bounds__(256) void compact_slabs(const uint32_t *counts, con
 // flight instead of one round trip per 64 records.
 constexpr int kRadixBlock = 1024;        // records per block, 8-bit digits
 constexpr int kRadixBlock11 = 8192;      // records per block, 9..11-bit digits (at most 2048 digits per block)
-constexpr int kRadixR = 8;               // records per lane in flight
+constexpr int kRadixR = 16;              // records per lane in flight
 
 template <int DB, int BLK>
 __global__ __launch_bounds__(64) void radix_hist(const uint64_t *in, uint64_t n, uint32_t shift, uint32_t *ghist,
