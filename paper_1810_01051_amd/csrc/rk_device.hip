@@ -156,16 +156,25 @@ __global__ __launch_bounds__(64) void radix_hist(const uint64_t *in, uint64_t n,
 }
 
 // STRIP: the pass is the last one, and writes each record's position only
-// (the final positions array) instead of the record.
+// (the final positions array) instead of the record.  Ranks within 64
+// records: every lane ORs its bit into the LDS mask of its digit, reads the
+// mask back (the lanes holding that digit) and counts the lower ones; the
+// highest lane of each digit advances the digit's cursor and clears the
+// mask.  The block is one wave, whose LDS operations take effect in issue
+// order, so no barrier is needed between those steps.
 template <int DB, int BLK, bool STRIP>
 __global__ __launch_bounds__(64) void radix_scatter(const uint64_t *in, uint64_t n, uint32_t shift,
                                                     const uint64_t *goff, uint64_t nblk, uint64_t *out) {
   constexpr uint32_t ND = 1u << DB;
   __shared__ uint64_t run[ND];
-  for (uint32_t d = threadIdx.x; d < ND; d += 64) run[d] = goff[(uint64_t)d * nblk + blockIdx.x];
+  __shared__ unsigned long long grp[ND];
+  for (uint32_t d = threadIdx.x; d < ND; d += 64) {
+    run[d] = goff[(uint64_t)d * nblk + blockIdx.x];
+    grp[d] = 0;
+  }
   __syncthreads();
   const uint32_t lane = threadIdx.x;
-  const uint64_t lt_mask = (1ull << lane) - 1ull;
+  const uint64_t me = 1ull << lane, lt_mask = me - 1ull;
   const uint64_t base = (uint64_t)blockIdx.x * BLK;
   for (int j = 0; j < BLK; j += 64 * kRadixR) {
     uint64_t recs[kRadixR];
@@ -177,24 +186,16 @@ __global__ __launch_bounds__(64) void radix_scatter(const uint64_t *in, uint64_t
 #pragma unroll
     for (int u = 0; u < kRadixR; ++u) {
       const uint64_t rec = recs[u];
-      const bool valid = rec != ~0ull;
+      if (rec == ~0ull) continue;
       const uint32_t dg = (uint32_t)(rec >> shift) & (ND - 1u);
-      // lanes holding the same digit
-      uint64_t peers = ballot(valid);
-#pragma unroll
-      for (int bit = 0; bit < DB; ++bit) {
-        const uint64_t ones = ballot(valid && ((dg >> bit) & 1u));
-        peers &= ((dg >> bit) & 1u) ? ones : ~ones;
+      atomicOr(&grp[dg], (unsigned long long)me);
+      const uint64_t peers = grp[dg];
+      const uint64_t at = run[dg];
+      out[at + __builtin_popcountll(peers & lt_mask)] = STRIP ? (rec & kPosMask) : rec;
+      if ((peers >> lane) == 1ull) {
+        run[dg] = at + __builtin_popcountll(peers);
+        grp[dg] = 0;
       }
-      const uint32_t rank = __builtin_popcountll(peers & lt_mask);
-      const uint64_t dst = run[dg] + rank;
-      __syncthreads();
-      if (valid) {
-        out[dst] = STRIP ? (rec & kPosMask) : rec;
-        // the highest lane of each digit group advances the cursor
-        if ((peers >> lane) == 1ull) run[dg] += __builtin_popcountll(peers);
-      }
-      __syncthreads();
     }
   }
 }

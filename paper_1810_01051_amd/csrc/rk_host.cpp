@@ -182,6 +182,17 @@ static uint32_t put_bytes(std::vector<uint8_t> &body, const void *p, size_t byte
   return off;
 }
 
+// Record of the entries [i, j) sharing one key: one entry inline; a run of
+// one pattern under several ids (identical bytes: one comparison, then a hit
+// per id) as such when it fits that encoding; else a plain run.
+static uint64_t key_record(const std::vector<Entry> &ents, size_t i, size_t j) {
+  if (j - i == 1) return slot_inline(ents[i].pid, ents[i].off_m);
+  bool same = j - i <= kSameMaxCount && i < kSameMaxFirst;
+  for (size_t q = i + 1; q < j && same; ++q) same = ents[q].off_m == ents[i].off_m;
+  if (same) return slot_same((uint32_t)i, (uint32_t)(j - i), ents[i].off_m);
+  return slot_run((uint32_t)i, (uint32_t)(j - i));
+}
+
 // Serialises one group.  Returns false if its keys do not fit a cuckoo table
 // of at most 2^kMaxTableBits slots or it has more entries than a run can
 // address (the caller then splits the group).
@@ -283,7 +294,7 @@ static bool emit_group(const GroupIn &G, GroupBody &out) {
       const uint32_t h = (uint32_t)P[i].key;
       uint32_t s = ck_slot1(h, sh);
       if (out.tab[s] != h) s = ck_slot2(h, sh);
-      rec[s] = (j - i == 1) ? slot_inline(ents[i].pid, ents[i].off_m) : slot_run((uint32_t)i, (uint32_t)(j - i));
+      rec[s] = key_record(ents, i, j);
       i = j;
     }
     D.ht_mask = S - 1;
@@ -298,7 +309,7 @@ static bool emit_group(const GroupIn &G, GroupBody &out) {
       uint32_t s = ht_slot(P[i].key, S - 1);
       while (keys[s] != kEmptyKey) s = (s + 1) & (S - 1);
       keys[s] = P[i].key;
-      vals[s] = (j - i == 1) ? slot_inline(ents[i].pid, ents[i].off_m) : slot_run((uint32_t)i, (uint32_t)(j - i));
+      vals[s] = key_record(ents, i, j);
       i = j;
     }
     std::vector<uint8_t> ht(S * 16);

@@ -70,13 +70,24 @@ __host__ __device__ inline uint32_t om_off(uint32_t om) { return om & (kGroupPat
 // Record of a key (list kinds: in the key table; table kinds: per cuckoo
 // slot): the run of entries with that key, or the single entry inline.
 //   bit 63 set : one entry, pattern id in bits 32..55, off_m in bits 0..31
-//   bit 63 clear: count in bits 32..62 (0: no entry), first entry in bits 0..31
+//   bits 63-62 = 01: a run of identical patterns (one pattern under several
+//                ids): count - 1 in bits 54..61, first entry in bits 32..53,
+//                their shared off_m in bits 0..31
+//   bits 63-62 = 00: count in bits 32..61 (0: no entry), first entry in bits 0..31
 __host__ __device__ inline uint64_t slot_inline(uint32_t pid, uint32_t off_m) {
   return (1ull << 63) | ((uint64_t)pid << 32) | off_m;
 }
 __host__ __device__ inline uint64_t slot_run(uint32_t first, uint32_t count) {
   return ((uint64_t)count << 32) | first;
 }
+constexpr uint32_t kSameMaxCount = 256, kSameMaxFirst = 1u << 22;
+__host__ __device__ inline uint64_t slot_same(uint32_t first, uint32_t count, uint32_t off_m) {
+  return (1ull << 62) | ((uint64_t)(count - 1u) << 54) | ((uint64_t)first << 32) | off_m;
+}
+__host__ __device__ inline bool rec_one_pattern(uint64_t rec) { return (rec >> 62) != 0; }  // inline or identical run
+__host__ __device__ inline bool rec_same(uint64_t rec) { return (rec >> 62) == 1u; }
+__host__ __device__ inline uint32_t same_count(uint64_t rec) { return (uint32_t)((rec >> 54) & 0xFFu) + 1u; }
+__host__ __device__ inline uint32_t same_first(uint64_t rec) { return (uint32_t)(rec >> 32) & (kSameMaxFirst - 1u); }
 
 // Slot of a key in a group's key table (the host builds it, the kernel probes it).
 __host__ __device__ inline uint32_t ht_slot(uint64_t key, uint32_t mask) {

@@ -866,7 +866,7 @@ __device__ __forceinline__ bool entry_matches(const uint8_t *gimg, const BucketD
   return window_equals_global(gtext + x, pat, m);
 }
 
-// Verifies the entries of a record (slot_inline / slot_run) for the candidate
+// Verifies the entries of a plain run record (slot_run) for the candidate
 // window ending at *end (global end index e).  Consecutive entries with the
 // same pattern bytes (identical patterns under several ids) share one
 // comparison.  Returns the number of matching entries; bit i of mask is set
@@ -874,10 +874,6 @@ __device__ __forceinline__ bool entry_matches(const uint8_t *gimg, const BucketD
 __device__ __forceinline__ uint32_t verify_run(const uint8_t *gimg, const BucketDesc &D, uint64_t rec, const uint8_t *end,
                                                int64_t e, const uint8_t *gtext, uint32_t &mask) {
   mask = 0;
-  if (rec >> 63) {
-    mask = entry_matches(gimg, D, (uint32_t)rec, end, e, gtext) ? 1u : 0u;
-    return mask;
-  }
   const Entry *ent = (const Entry *)(gimg + D.ent_off);
   const uint32_t first = (uint32_t)rec, cnt = (uint32_t)(rec >> 32);
   uint32_t nh = 0, prev = kNoLink;
@@ -913,6 +909,20 @@ __device__ __forceinline__ void write_hits(const uint8_t *gimg, const BucketDesc
     return;
   }
   const Entry *ent = (const Entry *)(gimg + D.ent_off);
+  if (rec_same(rec)) {
+    // one pattern under several ids: a hit for each
+    if (mask) {
+      const uint32_t first = same_first(rec), cnt = same_count(rec);
+      const uint64_t x = (uint64_t)(e - (int64_t)om_len((uint32_t)rec) + 1);
+      for (uint32_t i = 0; i < cnt; ++i) {
+        const uint32_t pid = ent[first + i].pid;
+        if (o < cap) slab[o] = ((uint64_t)pid << kPosBits) | x;
+        if (pid_counts) atomicAdd(pid_counts + pid, 1ull);
+        ++o;
+      }
+    }
+    return;
+  }
   const uint32_t first = (uint32_t)rec, cnt = (uint32_t)(rec >> 32);
   for (uint32_t i = 0; i < cnt; ++i) {
     const Entry en = ent[first + i];
@@ -1093,7 +1103,7 @@ __device__ __forceinline__ void candidate_phase(Bits<C> &bits, const BucketDesc 
         for (int j = 0; j < Q; ++j) {
           if (!fnd[j]) rec[j] = 0;
           hd[j][0] = hd[j][1] = hd[j][2] = hd[j][3] = 0;
-          if ((uint32_t)j < q && (rec[j] >> 63)) {
+          if ((uint32_t)j < q && rec_one_pattern(rec[j])) {
             const uint32_t *pw = (const uint32_t *)(gimg + D.pat_off + om_off((uint32_t)rec[j]));
             hd[j][0] = pw[0];
             hd[j][1] = pw[1];
@@ -1104,15 +1114,16 @@ __device__ __forceinline__ void candidate_phase(Bits<C> &bits, const BucketDesc 
 #pragma unroll
         for (int j = 0; j < Q; ++j) {
           if ((uint32_t)j >= q || !rec[j]) continue;
-          if (rec[j] >> 63) {
-            // one pattern: starts inside the text, bytes equal (Sec. 3.1)
+          if (rec_one_pattern(rec[j])) {
+            // one pattern (under one id, or under several: a hit per id):
+            // starts inside the text, bytes equal (Sec. 3.1)
             const uint32_t om = (uint32_t)rec[j], mj = om_len(om);
             const int64_t x = e[j] - (int64_t)mj + 1;
             const uint8_t *pat = gimg + D.pat_off + om_off(om);
             const bool ok = x >= 0 && (mj <= kFront ? window_equals_head(end[j], hd[j], pat, mj)
                                                      : window_equals_global(gtext + x, pat, mj));
-            hm[j] = ok ? 1u : 0u;
-            nh[j] = hm[j];
+            hm[j] = ok ? 0xFFFFFFFFu : 0u;
+            nh[j] = ok ? (rec_same(rec[j]) ? same_count(rec[j]) : 1u) : 0u;
           } else {
             nh[j] = verify_run(gimg, D, rec[j], end[j], e[j], gtext, hm[j]);
           }

@@ -217,6 +217,28 @@ def test_large_pattern_set(ctx, rk, mode):
 
 
 @pytest.mark.parametrize("mode", MODES)
+def test_shared_keys_and_identical_runs(ctx, rk, mode):
+    """Patterns of several lengths in one length class share the class's key
+    (the hash of their last l bytes, l the class's shortest length): sets
+    whose members end in the same bytes form runs of different patterns under
+    one key, and copies of one pattern form runs of one pattern under several
+    ids; both against the oracle, with hits dense enough that every tile has
+    candidates."""
+    g = rkgen.rng(57, 0 if mode == "screen" else 1)
+    n = 1 << 20
+    text = rkgen.iid_text(g, n, rkgen.ACGT)
+    pats = []
+    for o in g.integers(0, n - 64, size=40):
+        o = int(o)
+        for m in (4, 5, 7, 9, 12, 15, 16, 20, 31, 33, 48, 64):
+            pats.append(text[o + 64 - m:o + 64].tobytes())  # all end at the same byte
+    pats += pats[:30] * 3  # one pattern under four ids
+    pats += [b"ACGT", b"ACGT", b"CGTA"]
+    got = run(ctx, rk, text, pats, mode)
+    assert_same(got, oracle.search(text, pats, threads=8), mode)
+
+
+@pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("cfg", [0, 1, 2, 3])
 def test_tile_seams_every_geometry(ctx, rk, mode, cfg):
     """Occurrences planted across tile and thread seams, first and last window."""
