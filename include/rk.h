@@ -115,8 +115,9 @@ typedef enum {
                            rescanned by rk_collect. */
   RK_OPT_TILE_CFG = 2,  /* scan geometry index into the built-in table (see rk_tile_cfg);
                            -1 = autotuned / default */
-  RK_OPT_GRID = 3,      /* workgroups of the persistent scan (0 = default: as many as are
-                           resident on every CU at once, from the kernel's occupancy) */
+  RK_OPT_GRID = 3,      /* workgroups of the scan, which strides over the tiles (0 = default:
+                           32 times as many as are resident on every CU at once for the
+                           single-pattern scan, as many as are resident for the others) */
   RK_OPT_PROFILE = 4,   /* 1: time every scan launch with HIP events (rk_ctx_profile) */
   RK_OPT_QUEUE = 5      /* 1: scan pulls tiles from an atomic work queue; 0: static striding;
                            -1 (default): queue for multi-instance plans only */

@@ -373,6 +373,9 @@ static uint32_t scan_grid(rk_ctx *ctx, int cfg, int fam, uint32_t lds, uint64_t 
   return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(g, nitems));
 }
 
+// Blocks per resident slot of the single-bucket scan's grid.
+constexpr uint32_t kListGridMul = 32;
+
 // Fills ScanParams common to the count pass and the rescan of part pi.
 static void base_params(const rk_plan *plan, const Layout &L, uint32_t pi, uint8_t *sc, ScanParams &p) {
   memset(&p, 0, sizeof p);
@@ -454,11 +457,14 @@ rk_status count_enqueue(rk_ctx *ctx, const rk_plan *plan, const uint8_t *text, u
     lp.ovf_count = (uint32_t *)(sc + L.ctr + kCtrOvf);
     lp.ovf_list = (uint64_t *)(sc + L.ovf);
     lp.pid_counts = (unsigned long long *)counts;
+    // The grid is kListGridMul times what is resident at once: blocks of a
+    // few tiles each, dispatched as others finish, scan faster than one
+    // persistent block per slot (config 2: 5.7 against 5.2 TB/s).
     uint32_t grid = ctx->grid;
     if (!grid) {
       int blocks = 0;
       if (list_scan(plan->cfg, plan->fam, nullptr, 0, nullptr, &blocks) != hipSuccess || blocks < 1) blocks = 1;
-      grid = (uint32_t)ctx->num_cu * (uint32_t)blocks;
+      grid = (uint32_t)ctx->num_cu * (uint32_t)blocks * kListGridMul;
     }
     grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(grid, L.T));
     e = prof_begin(ctx, s, 0, &slot);
