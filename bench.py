@@ -166,10 +166,11 @@ def make_ctx(rk, args):
     return ctx
 
 
-def stream_read_ceiling(ctx, text, grids=(256, 512, 1024)):
+def stream_read_ceiling(ctx, text, grids=(256, 512, 1024, 2048, 8192, 32768)):
     """Read bandwidth of the plain streaming kernel (rk_stream_read: every
-    16-byte block of the text read once, no compute) over the same buffer:
-    the practical HBM read ceiling the scan is compared with."""
+    16-byte block of the text read once, no compute) over the same buffer,
+    best of several grid sizes: the practical HBM read ceiling the scan is
+    compared with."""
     import ctypes
     import torch
     from paper_1810_01051_amd import _lib

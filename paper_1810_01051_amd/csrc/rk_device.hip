@@ -200,6 +200,91 @@ __global__ __launch_bounds__(64) void radix_scatter(const uint64_t *in, uint64_t
   }
 }
 
+// ------------------------------- one radix pass reading the staging slabs
+// For dense hits the compaction is skipped: the records of a part's tiles
+// are read where the count pass left them, tile by tile in tile order (the
+// order the compaction would have produced), a block taking G consecutive
+// tiles.  Tile t's counts[t] records are its slab (slabs + (t - tile0) * S)
+// when they fit, else those of the collect's rescan, written at tile_off[t]
+// of the direct buffer.
+__device__ __forceinline__ const uint64_t *tile_records(const TileSrc &src, uint64_t t, uint32_t &c) {
+  c = __builtin_amdgcn_readfirstlane(src.counts[t]);
+  return c <= src.S ? src.slabs + (t - src.tile0) * src.S : src.direct + src.tile_off[t];
+}
+
+template <int DB>
+__global__ __launch_bounds__(64) void radix_hist_tiles(TileSrc src, uint32_t *ghist, uint64_t nblk) {
+  constexpr uint32_t ND = 1u << DB;
+  __shared__ uint32_t h[ND];
+  for (uint32_t i = threadIdx.x; i < ND; i += 64) h[i] = 0;
+  __syncthreads();
+  const uint64_t t0 = src.tile0 + (uint64_t)blockIdx.x * src.G;
+  const uint64_t t1 = min(t0 + src.G, src.tile0 + src.ntiles);
+  for (uint64_t t = t0; t < t1; ++t) {
+    uint32_t c;
+    const uint64_t *in = tile_records(src, t, c);
+    for (uint32_t j = 0; j < c; j += 64 * kRadixR) {
+      uint64_t rec[kRadixR];
+#pragma unroll
+      for (int u = 0; u < kRadixR; ++u) {
+        const uint32_t i = j + u * 64 + threadIdx.x;
+        rec[u] = i < c ? in[i] : ~0ull;
+      }
+#pragma unroll
+      for (int u = 0; u < kRadixR; ++u)
+        if (rec[u] != ~0ull) atomicAdd(&h[(rec[u] >> kPosBits) & (ND - 1u)], 1u);
+    }
+  }
+  __syncthreads();
+  for (uint32_t d = threadIdx.x; d < ND; d += 64) ghist[(uint64_t)d * nblk + src.blk0 + blockIdx.x] = h[d];
+}
+
+// Positions of the records to their final place (the last and only pass),
+// ranked as in radix_scatter.
+template <int DB>
+__global__ __launch_bounds__(64) void radix_scatter_tiles(TileSrc src, const uint64_t *goff, uint64_t nblk,
+                                                          uint64_t *out) {
+  constexpr uint32_t ND = 1u << DB;
+  __shared__ uint64_t run[ND];
+  __shared__ unsigned long long grp[ND];
+  const uint64_t b = src.blk0 + blockIdx.x;
+  for (uint32_t d = threadIdx.x; d < ND; d += 64) {
+    run[d] = goff[(uint64_t)d * nblk + b];
+    grp[d] = 0;
+  }
+  __syncthreads();
+  const uint32_t lane = threadIdx.x;
+  const uint64_t me = 1ull << lane, lt_mask = me - 1ull;
+  const uint64_t t0 = src.tile0 + (uint64_t)blockIdx.x * src.G;
+  const uint64_t t1 = min(t0 + src.G, src.tile0 + src.ntiles);
+  for (uint64_t t = t0; t < t1; ++t) {
+    uint32_t c;
+    const uint64_t *in = tile_records(src, t, c);
+    for (uint32_t j = 0; j < c; j += 64 * kRadixR) {
+      uint64_t recs[kRadixR];
+#pragma unroll
+      for (int u = 0; u < kRadixR; ++u) {
+        const uint32_t i = j + u * 64 + lane;
+        recs[u] = i < c ? in[i] : ~0ull;
+      }
+#pragma unroll
+      for (int u = 0; u < kRadixR; ++u) {
+        const uint64_t rec = recs[u];
+        if (rec == ~0ull) continue;
+        const uint32_t dg = (uint32_t)(rec >> kPosBits) & (ND - 1u);
+        atomicOr(&grp[dg], (unsigned long long)me);
+        const uint64_t peers = grp[dg];
+        const uint64_t at = run[dg];
+        out[at + __builtin_popcountll(peers & lt_mask)] = rec & kPosMask;
+        if ((peers >> lane) == 1ull) {
+          run[dg] = at + __builtin_popcountll(peers);
+          grp[dg] = 0;
+        }
+      }
+    }
+  }
+}
+
 // offsets[j] = start of pid j = the scanned histogram at (digit j, block 0),
 // for a sort that took one pass over the whole pid; offsets[k] = n.
 __global__ void offsets_from_digits(const uint64_t *goff, uint64_t nblk, uint32_t k, uint64_t n, uint64_t *offsets) {
@@ -343,6 +428,44 @@ hipError_t launch_radix(uint64_t *a, uint64_t *b, uint64_t n, uint32_t k, uint32
   hipError_t e = launch_pid_offsets(src, n, k, offsets, s);
   if (e != hipSuccess) return e;
   return launch_strip(src, n, positions, s);
+}
+
+template <int DB>
+static hipError_t radix_tiles_pass(const TileSrc *parts, uint32_t nparts, uint64_t nblk, uint64_t n, uint32_t k,
+                                   uint32_t *ghist, uint64_t *goff, uint64_t *tmp, uint64_t *offsets,
+                                   uint64_t *positions, hipStream_t s) {
+  for (uint32_t i = 0; i < nparts; ++i) {
+    const uint64_t nb = (parts[i].ntiles + parts[i].G - 1) / parts[i].G;
+    if (nb) hipLaunchKernelGGL((radix_hist_tiles<DB>), dim3((uint32_t)nb), dim3(64), 0, s, parts[i], ghist, nblk);
+  }
+  hipError_t e = launch_exclusive_scan(ghist, (1ull << DB) * nblk, goff, tmp, nullptr, s);
+  if (e != hipSuccess) return e;
+  for (uint32_t i = 0; i < nparts; ++i) {
+    const uint64_t nb = (parts[i].ntiles + parts[i].G - 1) / parts[i].G;
+    if (nb)
+      hipLaunchKernelGGL((radix_scatter_tiles<DB>), dim3((uint32_t)nb), dim3(64), 0, s, parts[i], goff, nblk,
+                         positions);
+  }
+  const uint64_t th = (uint64_t)k + 1;
+  hipLaunchKernelGGL(offsets_from_digits, dim3((uint32_t)((th + 255) / 256)), dim3(256), 0, s, goff, nblk, k, n,
+                     offsets);
+  return hipGetLastError();
+}
+
+// The one-pass sort (up to 2,048 pids) over records read from the staging
+// slabs (see TileSrc); parts[i].G and blk0 set by the caller, nblk the total
+// block count (the histograms hold 2^pid_bits * nblk entries).
+hipError_t launch_radix_tiles(const TileSrc *parts, uint32_t nparts, uint64_t nblk, uint64_t n, uint32_t k,
+                              uint32_t *ghist, uint64_t *goff, uint64_t *tmp, uint64_t *offsets, uint64_t *positions,
+                              hipStream_t s) {
+  uint32_t pid_bits = 0;
+  while (pid_bits < 32 && (1ull << pid_bits) < k) ++pid_bits;
+  if (n == 0) return hipSuccess;
+  if (pid_bits <= 8) return radix_tiles_pass<8>(parts, nparts, nblk, n, k, ghist, goff, tmp, offsets, positions, s);
+  if (pid_bits == 9) return radix_tiles_pass<9>(parts, nparts, nblk, n, k, ghist, goff, tmp, offsets, positions, s);
+  if (pid_bits == 10) return radix_tiles_pass<10>(parts, nparts, nblk, n, k, ghist, goff, tmp, offsets, positions, s);
+  if (pid_bits == 11) return radix_tiles_pass<11>(parts, nparts, nblk, n, k, ghist, goff, tmp, offsets, positions, s);
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_pid_offsets(const uint64_t *sorted, uint64_t n, uint32_t k, uint64_t *offsets, hipStream_t s) {

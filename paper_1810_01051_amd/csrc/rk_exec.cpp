@@ -310,6 +310,7 @@ rk_status make_layout(rk_ctx *ctx, const rk_plan *plan, uint64_t n, Layout &L) {
 
 struct WorkLayout {
   uint64_t nblk = 0, a = 0, b = 0, ghist = 0, goff = 0, tmp = 0, total = 0;
+  uint64_t nh = 0;  // histogram entries the work holds
 };
 
 // work of a k-pattern collect: the compacted records (a), the ping-pong
@@ -333,6 +334,7 @@ static WorkLayout work_layout(uint64_t total, uint32_t k) {
   w.goff = take(nh * 8);
   w.tmp = take(scan_tmp_words(nh) * 8);
   w.total = o;
+  w.nh = nh;
   return w;
 }
 
@@ -586,7 +588,35 @@ rk_status collect_enqueue_known(rk_ctx *ctx, const rk_plan *plan, uint64_t n, vo
   if (e != hipSuccess) return hip_err(ctx, e, "tile scan");
   WorkLayout WL = work_layout(total, k);
   uint64_t *target = k == 1 ? positions : (uint64_t *)((uint8_t *)work + WL.a);
+  // Dense hits (at least 64 per tile on average) up to 2,048 patterns: the
+  // sort reads the records from the slabs, G tiles per radix block (about
+  // 8,192 records), and the compaction is skipped; the rescan below still
+  // writes the overflowed tiles' records to the work buffer.
+  TileSrc tsrc[kMaxParts];
+  uint32_t ntsrc = 0;
+  uint64_t tblk = 0;
+  bool from_slabs = false;
+  if (k > 1 && k <= 2048 && total >= 64 * L.T && L.parts.size() <= (size_t)kMaxParts) {
+    uint32_t bits = 8;
+    while ((1u << bits) < k) ++bits;
+    const uint32_t G = (uint32_t)std::max<uint64_t>(1, (8192 * L.T + total - 1) / total);
+    for (const PartRun &r : L.parts) {
+      TileSrc &t = tsrc[ntsrc++];
+      t.counts = (const uint32_t *)(sc + L.counts);
+      t.tile_off = tile_off;
+      t.slabs = (const uint64_t *)(sc + r.slabs);
+      t.direct = target;
+      t.tile0 = r.tile0;
+      t.ntiles = r.ntiles;
+      t.blk0 = tblk;
+      t.S = r.S;
+      t.G = G;
+      tblk += (r.ntiles + G - 1) / G;
+    }
+    from_slabs = tblk > 0 && (1ull << bits) * tblk <= WL.nh;
+  }
   for (const PartRun &r : L.parts) {
+    if (from_slabs) break;
     e = launch_compact((const uint32_t *)(sc + L.counts) + r.tile0, tile_off + r.tile0, r.ntiles,
                        (const uint64_t *)(sc + r.slabs), r.S, target, s);
     if (e != hipSuccess) return hip_err(ctx, e, "compact");
@@ -626,8 +656,12 @@ rk_status collect_enqueue_known(rk_ctx *ctx, const rk_plan *plan, uint64_t n, vo
     if (e != hipSuccess) return hip_err(ctx, e, "offsets");
   } else {
     uint8_t *wk = (uint8_t *)work;
-    e = launch_radix((uint64_t *)(wk + WL.a), (uint64_t *)(wk + WL.b), total, k, (uint32_t *)(wk + WL.ghist),
-                     (uint64_t *)(wk + WL.goff), (uint64_t *)(wk + WL.tmp), offsets, positions, s);
+    if (from_slabs)
+      e = launch_radix_tiles(tsrc, ntsrc, tblk, total, k, (uint32_t *)(wk + WL.ghist), (uint64_t *)(wk + WL.goff),
+                             (uint64_t *)(wk + WL.tmp), offsets, positions, s);
+    else
+      e = launch_radix((uint64_t *)(wk + WL.a), (uint64_t *)(wk + WL.b), total, k, (uint32_t *)(wk + WL.ghist),
+                       (uint64_t *)(wk + WL.goff), (uint64_t *)(wk + WL.tmp), offsets, positions, s);
     if (e != hipSuccess) return hip_err(ctx, e, "radix sort");
   }
   e = prof_end(ctx, s, slot);

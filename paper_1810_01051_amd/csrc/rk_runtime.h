@@ -207,6 +207,24 @@ hipError_t launch_compact(const uint32_t *counts, const uint64_t *offs, uint64_t
 uint64_t radix_blocks(uint64_t n);
 hipError_t launch_radix(uint64_t *a, uint64_t *b, uint64_t n, uint32_t k, uint32_t *ghist, uint64_t *goff,
                         uint64_t *tmp, uint64_t *offsets, uint64_t *positions, hipStream_t s);
+// Records of one part's tiles as the count pass left them (dense hits: the
+// collect sorts them without compacting them first): tile t's counts[t]
+// records are its slab (slabs + (t - tile0) * S) when they fit, else those
+// of the collect's rescan, at tile_off[t] of the direct buffer.  A radix
+// block takes G consecutive tiles; blk0 is the part's first block.
+struct TileSrc {
+  const uint32_t *counts;    // per tile, the pass's numbering
+  const uint64_t *tile_off;  // exclusive scan of counts
+  const uint64_t *slabs;     // the part's slabs [tile][S]
+  const uint64_t *direct;    // records of the rescanned tiles
+  uint64_t tile0, ntiles;    // the part's tiles
+  uint64_t blk0;             // global index of the part's first block
+  uint32_t S, G;
+};
+
+hipError_t launch_radix_tiles(const TileSrc *parts, uint32_t nparts, uint64_t nblk, uint64_t n, uint32_t k,
+                              uint32_t *ghist, uint64_t *goff, uint64_t *tmp, uint64_t *offsets, uint64_t *positions,
+                              hipStream_t s);
 hipError_t launch_pid_offsets(const uint64_t *sorted, uint64_t n, uint32_t k, uint64_t *offsets, hipStream_t s);
 hipError_t launch_strip(const uint64_t *rec, uint64_t n, uint64_t *pos, hipStream_t s);
 hipError_t launch_single_offsets(uint64_t *offsets, uint64_t total, hipStream_t s);
