@@ -131,7 +131,9 @@ constexpr int kRadixBlock = 1024;        // records per block, 8-bit digits
 constexpr int kRadixBlock11 = 8192;      // records per block, 9..11-bit digits (at most 2048 digits per block)
 constexpr int kRadixR = 16;              // records per lane in flight
 
-template <int DB, int BLK>
+// BM: the histogram is block-major (block b's ND counts contiguous, the
+// one-pass sorts); else digit-major (the 8-bit passes, scanned as one array).
+template <int DB, int BLK, bool BM>
 __global__ __launch_bounds__(64) void radix_hist(const uint64_t *in, uint64_t n, uint32_t shift, uint32_t *ghist,
                                                  uint64_t nblk) {
   constexpr uint32_t ND = 1u << DB;
@@ -152,7 +154,8 @@ __global__ __launch_bounds__(64) void radix_hist(const uint64_t *in, uint64_t n,
       if (rec[u] != ~0ull) atomicAdd(&h[(rec[u] >> shift) & (ND - 1u)], 1u);
   }
   __syncthreads();
-  for (uint32_t d = threadIdx.x; d < ND; d += 64) ghist[(uint64_t)d * nblk + blockIdx.x] = h[d];
+  for (uint32_t d = threadIdx.x; d < ND; d += 64)
+    ghist[BM ? (uint64_t)blockIdx.x * ND + d : (uint64_t)d * nblk + blockIdx.x] = h[d];
 }
 
 // STRIP: the pass is the last one, and writes each record's position only
@@ -162,14 +165,14 @@ __global__ __launch_bounds__(64) void radix_hist(const uint64_t *in, uint64_t n,
 // highest lane of each digit advances the digit's cursor and clears the
 // mask.  The block is one wave, whose LDS operations take effect in issue
 // order, so no barrier is needed between those steps.
-template <int DB, int BLK, bool STRIP>
+template <int DB, int BLK, bool STRIP, bool BM>
 __global__ __launch_bounds__(64) void radix_scatter(const uint64_t *in, uint64_t n, uint32_t shift,
                                                     const uint64_t *goff, uint64_t nblk, uint64_t *out) {
   constexpr uint32_t ND = 1u << DB;
   __shared__ uint64_t run[ND];
   __shared__ unsigned long long grp[ND];
   for (uint32_t d = threadIdx.x; d < ND; d += 64) {
-    run[d] = goff[(uint64_t)d * nblk + blockIdx.x];
+    run[d] = goff[BM ? (uint64_t)blockIdx.x * ND + d : (uint64_t)d * nblk + blockIdx.x];
     grp[d] = 0;
   }
   __syncthreads();
@@ -212,22 +215,24 @@ __device__ __forceinline__ const uint64_t *tile_records(const TileSrc &src, uint
   return c <= src.S ? src.slabs + (t - src.tile0) * src.S : src.direct + src.tile_off[t];
 }
 
+// Four waves per block, wave w taking the block's tiles w, w + 4, ...
 template <int DB>
-__global__ __launch_bounds__(64) void radix_hist_tiles(TileSrc src, uint32_t *ghist, uint64_t nblk) {
+__global__ __launch_bounds__(256) void radix_hist_tiles(TileSrc src, uint32_t *ghist, uint64_t nblk) {
   constexpr uint32_t ND = 1u << DB;
   __shared__ uint32_t h[ND];
-  for (uint32_t i = threadIdx.x; i < ND; i += 64) h[i] = 0;
+  for (uint32_t i = threadIdx.x; i < ND; i += 256) h[i] = 0;
   __syncthreads();
+  const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const uint64_t t0 = src.tile0 + (uint64_t)blockIdx.x * src.G;
   const uint64_t t1 = min(t0 + src.G, src.tile0 + src.ntiles);
-  for (uint64_t t = t0; t < t1; ++t) {
+  for (uint64_t t = t0 + w; t < t1; t += 4) {
     uint32_t c;
     const uint64_t *in = tile_records(src, t, c);
     for (uint32_t j = 0; j < c; j += 64 * kRadixR) {
       uint64_t rec[kRadixR];
 #pragma unroll
       for (int u = 0; u < kRadixR; ++u) {
-        const uint32_t i = j + u * 64 + threadIdx.x;
+        const uint32_t i = j + u * 64 + lane;
         rec[u] = i < c ? in[i] : ~0ull;
       }
 #pragma unroll
@@ -236,7 +241,7 @@ __global__ __launch_bounds__(64) void radix_hist_tiles(TileSrc src, uint32_t *gh
     }
   }
   __syncthreads();
-  for (uint32_t d = threadIdx.x; d < ND; d += 64) ghist[(uint64_t)d * nblk + src.blk0 + blockIdx.x] = h[d];
+  for (uint32_t d = threadIdx.x; d < ND; d += 256) ghist[(src.blk0 + blockIdx.x) * ND + d] = h[d];
 }
 
 // Positions of the records to their final place (the last and only pass),
@@ -249,7 +254,7 @@ __global__ __launch_bounds__(64) void radix_scatter_tiles(TileSrc src, const uin
   __shared__ unsigned long long grp[ND];
   const uint64_t b = src.blk0 + blockIdx.x;
   for (uint32_t d = threadIdx.x; d < ND; d += 64) {
-    run[d] = goff[(uint64_t)d * nblk + b];
+    run[d] = goff[b * ND + d];
     grp[d] = 0;
   }
   __syncthreads();
@@ -285,15 +290,108 @@ __global__ __launch_bounds__(64) void radix_scatter_tiles(TileSrc src, const uin
   }
 }
 
-// offsets[j] = start of pid j = the scanned histogram at (digit j, block 0),
-// for a sort that took one pass over the whole pid; offsets[k] = n.
-__global__ void offsets_from_digits(const uint64_t *goff, uint64_t nblk, uint32_t k, uint64_t n, uint64_t *offsets) {
-  const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j > k) return;
-  offsets[j] = j < k ? goff[j * nblk] : n;
+// Start of every (digit, block) of a one-pass sort from its block-major
+// histogram h[b][d] (nblk blocks, nd digits).  The blocks go in chunks of
+// kDigitChunk: digit_chunk_sums sums each chunk's rows (csum[c][d]);
+// digit_chunk_starts scans every digit's column over the chunks (crel[c][d]:
+// the counts of digit d in the chunks before c) and writes the digit totals;
+// digit_block_starts scans the totals across digits (where each digit starts)
+// and writes goff[b][d] = that start + crel + the counts of digit d in the
+// chunk's blocks before b.  Every access walks rows, 64 lanes over
+// consecutive digits.
+constexpr uint32_t kDigitChunk = 32;
+constexpr uint32_t kDigitWaves = 16;  // waves of digit_chunk_starts, one block per 64 digits
+
+__global__ __launch_bounds__(256) void digit_chunk_sums(const uint32_t *__restrict__ h, uint64_t nblk, uint32_t nd,
+                                                        uint32_t *__restrict__ csum) {
+  const uint64_t b0 = (uint64_t)blockIdx.x * kDigitChunk, b1 = min(b0 + kDigitChunk, nblk);
+  for (uint32_t d = threadIdx.x; d < nd; d += 256) {
+    uint32_t t = 0;
+#pragma unroll 8
+    for (uint64_t b = b0; b < b1; ++b) t += h[b * nd + d];
+    csum[(uint64_t)blockIdx.x * nd + d] = t;
+  }
 }
 
-// offsets[j] = first index of pid j in the sorted records; offsets[k] = n.
+// Block x covers digits 64x..64x+63 (one per lane); wave w takes a
+// contiguous run of chunks, sums it, then writes its chunks' exclusive
+// column prefixes from the sums of the waves before it.
+__global__ __launch_bounds__(64 * kDigitWaves) void digit_chunk_starts(const uint32_t *__restrict__ csum,
+                                                                        uint64_t nchunk, uint32_t nd,
+                                                                        uint64_t *__restrict__ crel,
+                                                                        uint64_t *__restrict__ dtot) {
+  __shared__ uint64_t part[kDigitWaves][64];
+  const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint32_t d = blockIdx.x * 64 + lane;
+  const uint64_t per = (nchunk + kDigitWaves - 1) / kDigitWaves;
+  const uint64_t c0 = min((uint64_t)w * per, nchunk), c1 = min(c0 + per, nchunk);
+  uint64_t t = 0;
+  if (d < nd)
+#pragma unroll 8
+    for (uint64_t c = c0; c < c1; ++c) t += csum[c * nd + d];
+  part[w][lane] = t;
+  __syncthreads();
+  uint64_t run = 0;
+  for (uint32_t i = 0; i < w; ++i) run += part[i][lane];
+  if (d < nd) {
+    for (uint64_t c = c0; c < c1; ++c) {
+      crel[c * nd + d] = run;
+      run += csum[c * nd + d];
+    }
+    if (w == kDigitWaves - 1) dtot[d] = run;
+  }
+}
+
+// Chunk x's blocks, digits 256y..256y+255.  Every block scans the digit
+// totals itself (nd is at most 2048); block (0, 0) also writes offsets (the digit is the whole pid of a
+// one-pass sort): offsets[j] = start of pid j, offsets[k] = n.
+__global__ __launch_bounds__(256) void digit_block_starts(const uint32_t *__restrict__ h, uint64_t nblk, uint32_t nd,
+                                                          const uint64_t *__restrict__ crel,
+                                                          const uint64_t *__restrict__ dtot,
+                                                          uint64_t *__restrict__ goff, uint32_t k, uint64_t n,
+                                                          uint64_t *__restrict__ offsets) {
+  constexpr uint32_t kPer = 8;  // digits per thread of the totals' scan (256 * 8 = 2048)
+  __shared__ uint64_t start[256 * kPer];
+  __shared__ uint64_t wsum[4];
+  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint64_t v[kPer], x = 0;
+#pragma unroll
+  for (uint32_t i = 0; i < kPer; ++i) {
+    const uint32_t d = threadIdx.x * kPer + i;
+    v[i] = d < nd ? dtot[d] : 0;
+    x += v[i];
+  }
+  const uint64_t mine = x;
+  for (int sh = 1; sh < 64; sh <<= 1) {
+    const uint64_t y = __shfl_up(x, sh, 64);
+    if (lane >= (uint32_t)sh) x += y;
+  }
+  if (lane == 63) wsum[wave] = x;
+  __syncthreads();
+  uint64_t before = x - mine;
+  for (uint32_t i = 0; i < wave; ++i) before += wsum[i];
+#pragma unroll
+  for (uint32_t i = 0; i < kPer; ++i) {
+    start[threadIdx.x * kPer + i] = before;
+    before += v[i];
+  }
+  __syncthreads();
+  if (blockIdx.x == 0 && blockIdx.y == 0)
+    for (uint32_t j = threadIdx.x; j <= k; j += 256) offsets[j] = j < k ? start[j] : n;
+  const uint64_t b0 = (uint64_t)blockIdx.x * kDigitChunk, b1 = min(b0 + kDigitChunk, nblk);
+  const uint32_t d = blockIdx.y * 256 + threadIdx.x;
+  if (d >= nd) return;
+  uint64_t run = start[d] + crel[(uint64_t)blockIdx.x * nd + d];
+  uint32_t c[kDigitChunk];
+#pragma unroll
+  for (uint32_t i = 0; i < kDigitChunk; ++i) c[i] = b0 + i < b1 ? h[(b0 + i) * nd + d] : 0;
+#pragma unroll
+  for (uint32_t i = 0; i < kDigitChunk; ++i) {
+    if (b0 + i < b1) goff[(b0 + i) * nd + d] = run;
+    run += c[i];
+  }
+}
+
 __global__ void pid_offsets(const uint64_t *sorted, uint64_t n, uint32_t k, uint64_t *offsets) {
   const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j > k) return;
@@ -378,19 +476,40 @@ hipError_t launch_compact(const uint32_t *counts, const uint64_t *offs, uint64_t
 
 uint64_t radix_blocks(uint64_t n) { return (n + kRadixBlock - 1) / kRadixBlock; }
 
+// Starts of every (digit, block) of a one-pass sort into goff (block-major,
+// like h) and of every digit into offsets (k + 1 entries); cs: work of
+// digit_cs_bytes(nblk * nd, nd) bytes.
+static hipError_t digit_offsets(const uint32_t *h, uint64_t nblk, uint32_t nd, uint64_t *goff, uint8_t *cs,
+                                uint32_t k, uint64_t n, uint64_t *offsets, hipStream_t s) {
+  if (nd > 2048 || k > nd) return hipErrorInvalidValue;
+  const uint64_t nchunk = (nblk + kDigitChunk - 1) / kDigitChunk;
+  uint32_t *csum = (uint32_t *)cs;
+  uint64_t *crel = (uint64_t *)(cs + ((nchunk * nd * 4 + 255) & ~255ull));
+  uint64_t *dtot = crel + nchunk * nd;
+  hipLaunchKernelGGL(digit_chunk_sums, dim3((uint32_t)nchunk), dim3(256), 0, s, h, nblk, nd, csum);
+  hipLaunchKernelGGL(digit_chunk_starts, dim3((nd + 63) / 64), dim3(64 * kDigitWaves), 0, s, csum, nchunk, nd, crel,
+                     dtot);
+  hipLaunchKernelGGL(digit_block_starts, dim3((uint32_t)nchunk, (nd + 255) / 256), dim3(256), 0, s, h, nblk, nd, crel,
+                     dtot, goff, k, n, offsets);
+  return hipGetLastError();
+}
+
+uint64_t digit_cs_bytes(uint64_t nh, uint32_t nd) {
+  const uint64_t cells = nh / kDigitChunk + nd;  // at least nchunk * nd for any nblk * nd <= nh
+  return ((cells * 4 + 255) & ~255ull) + cells * 8 + nd * 8;
+}
+
 template <int DB>
 static hipError_t radix_one_pass(const uint64_t *src, uint64_t n, uint32_t k, uint32_t *ghist, uint64_t *goff,
-                                 uint64_t *tmp, uint64_t *offsets, uint64_t *positions, hipStream_t s) {
+                                 uint8_t *cs, uint64_t *offsets, uint64_t *positions, hipStream_t s) {
   constexpr int BLK = DB == 8 ? kRadixBlock : kRadixBlock11;
   const uint64_t nblk = (n + BLK - 1) / BLK;
-  hipLaunchKernelGGL((radix_hist<DB, BLK>), dim3((uint32_t)nblk), dim3(64), 0, s, src, n, kPosBits, ghist, nblk);
-  hipError_t e = launch_exclusive_scan(ghist, (1ull << DB) * nblk, goff, tmp, nullptr, s);
+  hipLaunchKernelGGL((radix_hist<DB, BLK, true>), dim3((uint32_t)nblk), dim3(64), 0, s, src, n, kPosBits, ghist,
+                     nblk);
+  hipError_t e = digit_offsets(ghist, nblk, 1u << DB, goff, cs, k, n, offsets, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((radix_scatter<DB, BLK, true>), dim3((uint32_t)nblk), dim3(64), 0, s, src, n, kPosBits, goff,
-                     nblk, positions);
-  const uint64_t th = (uint64_t)k + 1;
-  hipLaunchKernelGGL(offsets_from_digits, dim3((uint32_t)((th + 255) / 256)), dim3(256), 0, s, goff, nblk, k, n,
-                     offsets);
+  hipLaunchKernelGGL((radix_scatter<DB, BLK, true, true>), dim3((uint32_t)nblk), dim3(64), 0, s, src, n, kPosBits,
+                     goff, nblk, positions);
   return hipGetLastError();
 }
 
@@ -403,23 +522,24 @@ static hipError_t radix_one_pass(const uint64_t *src, uint64_t n, uint32_t k, ui
 // for 256 * radix_blocks(n) entries, which also covers the one-pass digits
 // (at most 2048 per 8192-record block).
 hipError_t launch_radix(uint64_t *a, uint64_t *b, uint64_t n, uint32_t k, uint32_t *ghist, uint64_t *goff,
-                        uint64_t *tmp, uint64_t *offsets, uint64_t *positions, hipStream_t s) {
+                        uint64_t *tmp, uint8_t *cs, uint64_t *offsets, uint64_t *positions, hipStream_t s) {
   uint32_t pid_bits = 0;
   while (pid_bits < 32 && (1ull << pid_bits) < k) ++pid_bits;
   if (n == 0) return hipSuccess;
-  if (pid_bits <= 8) return radix_one_pass<8>(a, n, k, ghist, goff, tmp, offsets, positions, s);
-  if (pid_bits == 9) return radix_one_pass<9>(a, n, k, ghist, goff, tmp, offsets, positions, s);
-  if (pid_bits == 10) return radix_one_pass<10>(a, n, k, ghist, goff, tmp, offsets, positions, s);
-  if (pid_bits == 11) return radix_one_pass<11>(a, n, k, ghist, goff, tmp, offsets, positions, s);
+  if (pid_bits <= 8) return radix_one_pass<8>(a, n, k, ghist, goff, cs, offsets, positions, s);
+  if (pid_bits == 9) return radix_one_pass<9>(a, n, k, ghist, goff, cs, offsets, positions, s);
+  if (pid_bits == 10) return radix_one_pass<10>(a, n, k, ghist, goff, cs, offsets, positions, s);
+  if (pid_bits == 11) return radix_one_pass<11>(a, n, k, ghist, goff, cs, offsets, positions, s);
   uint64_t *src = a, *dst = b;
   const uint64_t nblk = radix_blocks(n);
   const uint32_t npass = (pid_bits + 7) / 8;
   for (uint32_t ps = 0; ps < npass; ++ps) {
     const uint32_t shift = kPosBits + 8 * ps;
-    hipLaunchKernelGGL((radix_hist<8, kRadixBlock>), dim3((uint32_t)nblk), dim3(64), 0, s, src, n, shift, ghist, nblk);
+    hipLaunchKernelGGL((radix_hist<8, kRadixBlock, false>), dim3((uint32_t)nblk), dim3(64), 0, s, src, n, shift, ghist,
+                       nblk);
     hipError_t e = launch_exclusive_scan(ghist, 256 * nblk, goff, tmp, nullptr, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((radix_scatter<8, kRadixBlock, false>), dim3((uint32_t)nblk), dim3(64), 0, s, src, n, shift,
+    hipLaunchKernelGGL((radix_scatter<8, kRadixBlock, false, false>), dim3((uint32_t)nblk), dim3(64), 0, s, src, n, shift,
                        goff, nblk, dst);
     uint64_t *t = src;
     src = dst;
@@ -432,13 +552,13 @@ hipError_t launch_radix(uint64_t *a, uint64_t *b, uint64_t n, uint32_t k, uint32
 
 template <int DB>
 static hipError_t radix_tiles_pass(const TileSrc *parts, uint32_t nparts, uint64_t nblk, uint64_t n, uint32_t k,
-                                   uint32_t *ghist, uint64_t *goff, uint64_t *tmp, uint64_t *offsets,
+                                   uint32_t *ghist, uint64_t *goff, uint8_t *cs, uint64_t *offsets,
                                    uint64_t *positions, hipStream_t s) {
   for (uint32_t i = 0; i < nparts; ++i) {
     const uint64_t nb = (parts[i].ntiles + parts[i].G - 1) / parts[i].G;
-    if (nb) hipLaunchKernelGGL((radix_hist_tiles<DB>), dim3((uint32_t)nb), dim3(64), 0, s, parts[i], ghist, nblk);
+    if (nb) hipLaunchKernelGGL((radix_hist_tiles<DB>), dim3((uint32_t)nb), dim3(256), 0, s, parts[i], ghist, nblk);
   }
-  hipError_t e = launch_exclusive_scan(ghist, (1ull << DB) * nblk, goff, tmp, nullptr, s);
+  hipError_t e = digit_offsets(ghist, nblk, 1u << DB, goff, cs, k, n, offsets, s);
   if (e != hipSuccess) return e;
   for (uint32_t i = 0; i < nparts; ++i) {
     const uint64_t nb = (parts[i].ntiles + parts[i].G - 1) / parts[i].G;
@@ -446,9 +566,6 @@ static hipError_t radix_tiles_pass(const TileSrc *parts, uint32_t nparts, uint64
       hipLaunchKernelGGL((radix_scatter_tiles<DB>), dim3((uint32_t)nb), dim3(64), 0, s, parts[i], goff, nblk,
                          positions);
   }
-  const uint64_t th = (uint64_t)k + 1;
-  hipLaunchKernelGGL(offsets_from_digits, dim3((uint32_t)((th + 255) / 256)), dim3(256), 0, s, goff, nblk, k, n,
-                     offsets);
   return hipGetLastError();
 }
 
@@ -456,15 +573,15 @@ static hipError_t radix_tiles_pass(const TileSrc *parts, uint32_t nparts, uint64
 // slabs (see TileSrc); parts[i].G and blk0 set by the caller, nblk the total
 // block count (the histograms hold 2^pid_bits * nblk entries).
 hipError_t launch_radix_tiles(const TileSrc *parts, uint32_t nparts, uint64_t nblk, uint64_t n, uint32_t k,
-                              uint32_t *ghist, uint64_t *goff, uint64_t *tmp, uint64_t *offsets, uint64_t *positions,
+                              uint32_t *ghist, uint64_t *goff, uint8_t *cs, uint64_t *offsets, uint64_t *positions,
                               hipStream_t s) {
   uint32_t pid_bits = 0;
   while (pid_bits < 32 && (1ull << pid_bits) < k) ++pid_bits;
   if (n == 0) return hipSuccess;
-  if (pid_bits <= 8) return radix_tiles_pass<8>(parts, nparts, nblk, n, k, ghist, goff, tmp, offsets, positions, s);
-  if (pid_bits == 9) return radix_tiles_pass<9>(parts, nparts, nblk, n, k, ghist, goff, tmp, offsets, positions, s);
-  if (pid_bits == 10) return radix_tiles_pass<10>(parts, nparts, nblk, n, k, ghist, goff, tmp, offsets, positions, s);
-  if (pid_bits == 11) return radix_tiles_pass<11>(parts, nparts, nblk, n, k, ghist, goff, tmp, offsets, positions, s);
+  if (pid_bits <= 8) return radix_tiles_pass<8>(parts, nparts, nblk, n, k, ghist, goff, cs, offsets, positions, s);
+  if (pid_bits == 9) return radix_tiles_pass<9>(parts, nparts, nblk, n, k, ghist, goff, cs, offsets, positions, s);
+  if (pid_bits == 10) return radix_tiles_pass<10>(parts, nparts, nblk, n, k, ghist, goff, cs, offsets, positions, s);
+  if (pid_bits == 11) return radix_tiles_pass<11>(parts, nparts, nblk, n, k, ghist, goff, cs, offsets, positions, s);
   return hipErrorInvalidValue;
 }
 

@@ -309,7 +309,7 @@ rk_status make_layout(rk_ctx *ctx, const rk_plan *plan, uint64_t n, Layout &L) {
 }
 
 struct WorkLayout {
-  uint64_t nblk = 0, a = 0, b = 0, ghist = 0, goff = 0, tmp = 0, total = 0;
+  uint64_t nblk = 0, a = 0, b = 0, ghist = 0, goff = 0, tmp = 0, cs = 0, total = 0;
   uint64_t nh = 0;  // histogram entries the work holds
 };
 
@@ -333,6 +333,7 @@ static WorkLayout work_layout(uint64_t total, uint32_t k) {
   w.ghist = take(nh * 4);
   w.goff = take(nh * 8);
   w.tmp = take(scan_tmp_words(nh) * 8);
+  w.cs = take(digit_cs_bytes(nh, 2048));
   w.total = o;
   w.nh = nh;
   return w;
@@ -589,8 +590,8 @@ rk_status collect_enqueue_known(rk_ctx *ctx, const rk_plan *plan, uint64_t n, vo
   WorkLayout WL = work_layout(total, k);
   uint64_t *target = k == 1 ? positions : (uint64_t *)((uint8_t *)work + WL.a);
   // Dense hits (at least 64 per tile on average) up to 2,048 patterns: the
-  // sort reads the records from the slabs, G tiles per radix block (about
-  // 8,192 records), and the compaction is skipped; the rescan below still
+  // sort reads the records from the slabs, G tiles per radix block (8,192 to
+  // 32,768 records), and the compaction is skipped; the rescan below still
   // writes the overflowed tiles' records to the work buffer.
   TileSrc tsrc[kMaxParts];
   uint32_t ntsrc = 0;
@@ -599,7 +600,11 @@ rk_status collect_enqueue_known(rk_ctx *ctx, const rk_plan *plan, uint64_t n, vo
   if (k > 1 && k <= 2048 && total >= 64 * L.T && L.parts.size() <= (size_t)kMaxParts) {
     uint32_t bits = 8;
     while ((1u << bits) < k) ++bits;
-    const uint32_t G = (uint32_t)std::max<uint64_t>(1, (8192 * L.T + total - 1) / total);
+    // records per block: 32,768 once there are 1,024 such blocks (longer runs
+    // per digit and block make the scatter's writes fuller lines), down to
+    // 8,192 for fewer hits (blocks enough to fill the chip)
+    const uint64_t rb = std::min<uint64_t>(32768, std::max<uint64_t>(8192, total / 1024));
+    const uint32_t G = (uint32_t)std::max<uint64_t>(1, (rb * L.T + total - 1) / total);
     for (const PartRun &r : L.parts) {
       TileSrc &t = tsrc[ntsrc++];
       t.counts = (const uint32_t *)(sc + L.counts);
@@ -658,10 +663,10 @@ rk_status collect_enqueue_known(rk_ctx *ctx, const rk_plan *plan, uint64_t n, vo
     uint8_t *wk = (uint8_t *)work;
     if (from_slabs)
       e = launch_radix_tiles(tsrc, ntsrc, tblk, total, k, (uint32_t *)(wk + WL.ghist), (uint64_t *)(wk + WL.goff),
-                             (uint64_t *)(wk + WL.tmp), offsets, positions, s);
+                             wk + WL.cs, offsets, positions, s);
     else
       e = launch_radix((uint64_t *)(wk + WL.a), (uint64_t *)(wk + WL.b), total, k, (uint32_t *)(wk + WL.ghist),
-                       (uint64_t *)(wk + WL.goff), (uint64_t *)(wk + WL.tmp), offsets, positions, s);
+                       (uint64_t *)(wk + WL.goff), (uint64_t *)(wk + WL.tmp), wk + WL.cs, offsets, positions, s);
     if (e != hipSuccess) return hip_err(ctx, e, "radix sort");
   }
   e = prof_end(ctx, s, slot);

@@ -206,7 +206,10 @@ hipError_t launch_compact(const uint32_t *counts, const uint64_t *offs, uint64_t
                           uint32_t slab_cap, uint64_t *out, hipStream_t s);
 uint64_t radix_blocks(uint64_t n);
 hipError_t launch_radix(uint64_t *a, uint64_t *b, uint64_t n, uint32_t k, uint32_t *ghist, uint64_t *goff,
-                        uint64_t *tmp, uint64_t *offsets, uint64_t *positions, hipStream_t s);
+                        uint64_t *tmp, uint8_t *cs, uint64_t *offsets, uint64_t *positions, hipStream_t s);
+// work bytes of the one-pass sorts' digit offsets for up to nh histogram
+// entries of nd digits
+uint64_t digit_cs_bytes(uint64_t nh, uint32_t nd);
 // Records of one part's tiles as the count pass left them (dense hits: the
 // collect sorts them without compacting them first): tile t's counts[t]
 // records are its slab (slabs + (t - tile0) * S) when they fit, else those
@@ -223,7 +226,7 @@ struct TileSrc {
 };
 
 hipError_t launch_radix_tiles(const TileSrc *parts, uint32_t nparts, uint64_t nblk, uint64_t n, uint32_t k,
-                              uint32_t *ghist, uint64_t *goff, uint64_t *tmp, uint64_t *offsets, uint64_t *positions,
+                              uint32_t *ghist, uint64_t *goff, uint8_t *cs, uint64_t *offsets, uint64_t *positions,
                               hipStream_t s);
 hipError_t launch_pid_offsets(const uint64_t *sorted, uint64_t n, uint32_t k, uint64_t *offsets, hipStream_t s);
 hipError_t launch_strip(const uint64_t *rec, uint64_t n, uint64_t *pos, hipStream_t s);
