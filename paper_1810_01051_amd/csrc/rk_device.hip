@@ -108,10 +108,18 @@ __global__ __launch_bounds__(kScanWG) void scan_local(const uint32_t *in, uint64
 }
 
 // ------------------------------------------------------------ slab compaction
-// One wave per tile: copy the tile's staged hits to their final offset
-// (tiles that overflowed their slab are rescanned instead).
+// Copy every tile's staged hits to their final offset (tiles that overflowed
+// their slab are rescanned instead).  offsets1 (a single pattern's offsets,
+// else null) gets {0, total} from the first thread.
+//
+// compact_slabs: one wave per tile.
 __global__ __launch_bounds__(256) void compact_slabs(const uint32_t *counts, const uint64_t *offs, uint64_t ntiles,
-                                                     const uint64_t *slabs, uint32_t slab_cap, uint64_t *out) {
+                                                     const uint64_t *slabs, uint32_t slab_cap, uint64_t *out,
+                                                     uint64_t *offsets1, uint64_t total) {
+  if (offsets1 && blockIdx.x == 0 && threadIdx.x == 0) {
+    offsets1[0] = 0;
+    offsets1[1] = total;
+  }
   const uint64_t t = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (t >= ntiles) return;
   const uint32_t c = counts[t];
@@ -119,6 +127,44 @@ __global__ __launch_bounds__(256) void compact_slabs(const uint32_t *counts, con
   const uint64_t *src = slabs + t * (uint64_t)slab_cap;
   uint64_t *dst = out + offs[t];
   for (uint32_t i = threadIdx.x & 63; i < c; i += 64) dst[i] = src[i];
+}
+
+// compact_sparse (fewer hits than tiles): a wave takes 64 tiles, a lane
+// each.  A lane copies its tile itself when it holds at most kLaneCopy
+// records; the wave copies the larger ones, one after the other.
+constexpr uint32_t kLaneCopy = 8;
+
+__global__ __launch_bounds__(256) void compact_sparse(const uint32_t *counts, const uint64_t *offs, uint64_t ntiles,
+                                                      const uint64_t *slabs, uint32_t slab_cap, uint64_t *out,
+                                                      uint64_t *offsets1, uint64_t total) {
+  if (offsets1 && blockIdx.x == 0 && threadIdx.x == 0) {
+    offsets1[0] = 0;
+    offsets1[1] = total;
+  }
+  const uint32_t lane = threadIdx.x & 63;
+  const uint64_t t0 = ((uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 64, t = t0 + lane;
+  const uint32_t c = t < ntiles ? counts[t] : 0u;
+  const bool ok = c != 0 && c <= slab_cap;
+  const uint64_t o = ok ? offs[t] : 0;
+  if (ok && c <= kLaneCopy) {
+    const uint64_t *src = slabs + t * (uint64_t)slab_cap;
+    uint64_t r[kLaneCopy];
+#pragma unroll
+    for (uint32_t i = 0; i < kLaneCopy; ++i)
+      if (i < c) r[i] = src[i];
+#pragma unroll
+    for (uint32_t i = 0; i < kLaneCopy; ++i)
+      if (i < c) out[o + i] = r[i];
+  }
+  uint64_t big = __ballot(ok && c > kLaneCopy);
+  while (big) {
+    const uint32_t l = (uint32_t)__builtin_ctzll(big);
+    big &= big - 1;
+    const uint32_t cl = __shfl(c, (int)l, 64);
+    const uint64_t ol = __shfl(o, (int)l, 64);
+    const uint64_t *src = slabs + (t0 + l) * (uint64_t)slab_cap;
+    for (uint32_t i = lane; i < cl; i += 64) out[ol + i] = src[i];
+  }
 }
 
 // -------------------------------------------------- stable radix by pattern id
@@ -413,13 +459,6 @@ __global__ void strip_positions(const uint64_t *rec, uint64_t n, uint64_t *pos) 
   if (i < n) pos[i] = rec[i] & kPosMask;
 }
 
-__global__ void single_offsets(uint64_t *offsets, uint64_t total) {
-  if (threadIdx.x == 0) {
-    offsets[0] = 0;
-    offsets[1] = total;
-  }
-}
-
 // ------------------------------------------------------------- window hashes
 __global__ void window_hashes_kernel(const uint8_t *text, uint64_t n, uint32_t m, const uint64_t *xs, uint64_t cnt,
                                      uint64_t *out) {
@@ -467,10 +506,15 @@ hipError_t launch_exclusive_scan(const uint32_t *in, uint64_t n, uint64_t *out, 
 }
 
 hipError_t launch_compact(const uint32_t *counts, const uint64_t *offs, uint64_t ntiles, const uint64_t *slabs,
-                          uint32_t slab_cap, uint64_t *out, hipStream_t s) {
+                          uint32_t slab_cap, uint64_t *out, bool sparse, uint64_t *offsets1, uint64_t total,
+                          hipStream_t s) {
   if (ntiles == 0) return hipSuccess;
-  hipLaunchKernelGGL(compact_slabs, dim3((uint32_t)((ntiles + 3) / 4)), dim3(256), 0, s, counts, offs, ntiles, slabs,
-                     slab_cap, out);
+  if (sparse)
+    hipLaunchKernelGGL(compact_sparse, dim3((uint32_t)((ntiles + 255) / 256)), dim3(256), 0, s, counts, offs, ntiles,
+                       slabs, slab_cap, out, offsets1, total);
+  else
+    hipLaunchKernelGGL(compact_slabs, dim3((uint32_t)((ntiles + 3) / 4)), dim3(256), 0, s, counts, offs, ntiles,
+                       slabs, slab_cap, out, offsets1, total);
   return hipGetLastError();
 }
 
@@ -597,10 +641,6 @@ hipError_t launch_strip(const uint64_t *rec, uint64_t n, uint64_t *pos, hipStrea
   return hipGetLastError();
 }
 
-hipError_t launch_single_offsets(uint64_t *offsets, uint64_t total, hipStream_t s) {
-  hipLaunchKernelGGL(single_offsets, dim3(1), dim3(64), 0, s, offsets, total);
-  return hipGetLastError();
-}
 
 hipError_t launch_window_hashes(const uint8_t *text, uint64_t n, uint32_t m, const uint64_t *xs, uint64_t cnt,
                                 uint64_t *out, hipStream_t s) {

@@ -620,11 +620,15 @@ rk_status collect_enqueue_known(rk_ctx *ctx, const rk_plan *plan, uint64_t n, vo
     }
     from_slabs = tblk > 0 && (1ull << bits) * tblk <= WL.nh;
   }
+  // a single pattern's offsets ({0, total}) come from the first compaction
+  uint64_t *offsets1 = k == 1 ? offsets : nullptr;
   for (const PartRun &r : L.parts) {
     if (from_slabs) break;
+    if (r.ntiles == 0) continue;
     e = launch_compact((const uint32_t *)(sc + L.counts) + r.tile0, tile_off + r.tile0, r.ntiles,
-                       (const uint64_t *)(sc + r.slabs), r.S, target, s);
+                       (const uint64_t *)(sc + r.slabs), r.S, target, total < L.T, offsets1, total, s);
     if (e != hipSuccess) return hip_err(ctx, e, "compact");
+    offsets1 = nullptr;
   }
   e = prof_end(ctx, s, slot);
   if (e != hipSuccess) return hip_err(ctx, e, "profiling event");
@@ -654,12 +658,10 @@ rk_status collect_enqueue_known(rk_ctx *ctx, const rk_plan *plan, uint64_t n, vo
       if (e != hipSuccess) return hip_err(ctx, e, "profiling event");
     }
   }
+  if (k == 1) return RK_OK;  // offsets written by the compaction
   e = prof_begin(ctx, s, 2, &slot);
   if (e != hipSuccess) return hip_err(ctx, e, "profiling event");
-  if (k == 1) {
-    e = launch_single_offsets(offsets, total, s);
-    if (e != hipSuccess) return hip_err(ctx, e, "offsets");
-  } else {
+  {
     uint8_t *wk = (uint8_t *)work;
     if (from_slabs)
       e = launch_radix_tiles(tsrc, ntsrc, tblk, total, k, (uint32_t *)(wk + WL.ghist), (uint64_t *)(wk + WL.goff),

@@ -202,8 +202,11 @@ hipError_t list_scan(int cfg, int fam, const ListParams *p, uint32_t grid, hipSt
 uint64_t scan_tmp_words(uint64_t n);
 hipError_t launch_exclusive_scan(const uint32_t *in, uint64_t n, uint64_t *out, uint64_t *tmp, uint64_t *total_dev,
                                  hipStream_t s);
+// sparse: fewer hits than tiles (a lane per tile); offsets1: a single
+// pattern's offsets, written {0, total}, or null
 hipError_t launch_compact(const uint32_t *counts, const uint64_t *offs, uint64_t ntiles, const uint64_t *slabs,
-                          uint32_t slab_cap, uint64_t *out, hipStream_t s);
+                          uint32_t slab_cap, uint64_t *out, bool sparse, uint64_t *offsets1, uint64_t total,
+                          hipStream_t s);
 uint64_t radix_blocks(uint64_t n);
 hipError_t launch_radix(uint64_t *a, uint64_t *b, uint64_t n, uint32_t k, uint32_t *ghist, uint64_t *goff,
                         uint64_t *tmp, uint8_t *cs, uint64_t *offsets, uint64_t *positions, hipStream_t s);
@@ -230,7 +233,6 @@ hipError_t launch_radix_tiles(const TileSrc *parts, uint32_t nparts, uint64_t nb
                               hipStream_t s);
 hipError_t launch_pid_offsets(const uint64_t *sorted, uint64_t n, uint32_t k, uint64_t *offsets, hipStream_t s);
 hipError_t launch_strip(const uint64_t *rec, uint64_t n, uint64_t *pos, hipStream_t s);
-hipError_t launch_single_offsets(uint64_t *offsets, uint64_t total, hipStream_t s);
 hipError_t launch_window_hashes(const uint8_t *text, uint64_t n, uint32_t m, const uint64_t *xs, uint64_t cnt,
                                 uint64_t *out, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint64_t words, uint32_t v, hipStream_t s);
