@@ -13,8 +13,12 @@
 namespace rk {
 
 // ---------------------------------------------------------- prefix sums (u64)
-// Exclusive scan of u32 counts into u64 offsets, three kernels:
-// per-block sums, a single-block scan of those sums, per-block local scans.
+// Exclusive scan of u32 counts into u64 offsets: per-block sums, then
+// per-block local scans that start from the sum of the blocks before them,
+// which up to kScanWG blocks add up themselves and beyond that a single-block
+// scan of the sums (scan_sums_single) hands them.  Every block is kScanWG
+// threads: a scan of one step is not held back until a whole CU is free while
+// another step's scan fills the chip.
 constexpr int kScanWG = 256;
 constexpr int kScanPer = 16;
 constexpr int kScanBlock = kScanWG * kScanPer;  // items per block
@@ -41,13 +45,13 @@ __global__ __launch_bounds__(kScanWG) void scan_block_sums(const uint32_t *in, u
 
 // Single block: exclusive scan of bsum[0..nb) in place; bsum[nb] = total;
 // also copies the total to *total_out if non-null.
-__global__ __launch_bounds__(1024) void scan_sums_single(uint64_t *bsum, uint64_t nb, uint64_t *total_out) {
-  __shared__ uint64_t wsum[16];
+__global__ __launch_bounds__(kScanWG) void scan_sums_single(uint64_t *bsum, uint64_t nb, uint64_t *total_out) {
+  __shared__ uint64_t wsum[kScanWG / 64];
   __shared__ uint64_t carry;
   if (threadIdx.x == 0) carry = 0;
   __syncthreads();
   const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (uint64_t base = 0; base < nb; base += 1024) {
+  for (uint64_t base = 0; base < nb; base += kScanWG) {
     const uint64_t i = base + threadIdx.x;
     const uint64_t v = i < nb ? bsum[i] : 0;
     uint64_t x = v;
@@ -58,7 +62,7 @@ __global__ __launch_bounds__(1024) void scan_sums_single(uint64_t *bsum, uint64_
     if (lane == 63) wsum[wave] = x;
     __syncthreads();
     uint64_t before = carry, tot = 0;
-    for (int k = 0; k < 16; ++k) {
+    for (int k = 0; k < kScanWG / 64; ++k) {
       before += (uint32_t)k < wave ? wsum[k] : 0;
       tot += wsum[k];
     }
@@ -73,11 +77,22 @@ __global__ __launch_bounds__(1024) void scan_sums_single(uint64_t *bsum, uint64_
   }
 }
 
-__global__ __launch_bounds__(kScanWG) void scan_local(const uint32_t *in, uint64_t n, const uint64_t *bsum,
-                                                      uint64_t *out) {
+// RAW: bsum holds the blocks' own sums (at most kScanWG blocks), each block
+// adds those before it, and the last one writes the total (bsum[nb], and
+// *total_out if non-null); else bsum is already scanned.
+template <bool RAW>
+__global__ __launch_bounds__(kScanWG) void scan_local(const uint32_t *in, uint64_t n, uint64_t *bsum, uint64_t nb,
+                                                      uint64_t *out, uint64_t *total_out) {
   __shared__ uint64_t wsum[kScanWG / 64];
+  __shared__ uint64_t pre[kScanWG / 64];
   const uint64_t base = (uint64_t)blockIdx.x * kScanBlock;
   const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (RAW) {
+    uint64_t p = threadIdx.x < blockIdx.x ? bsum[threadIdx.x] : 0;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) p += __shfl_xor(p, d, 64);
+    if (lane == 0) pre[wave] = p;
+  }
   // each thread owns kScanPer consecutive items
   uint32_t v[kScanPer];
   uint64_t s = 0;
@@ -95,7 +110,13 @@ __global__ __launch_bounds__(kScanWG) void scan_local(const uint32_t *in, uint64
   }
   if (lane == 63) wsum[wave] = x;
   __syncthreads();
-  uint64_t before = bsum[blockIdx.x];
+  uint64_t before = 0;
+  if (RAW) {
+#pragma unroll
+    for (int k = 0; k < kScanWG / 64; ++k) before += pre[k];
+  } else {
+    before = bsum[blockIdx.x];
+  }
 #pragma unroll
   for (int k = 0; k < kScanWG / 64; ++k) before += (uint32_t)k < wave ? wsum[k] : 0;
   uint64_t run = before + x - s;
@@ -104,6 +125,10 @@ __global__ __launch_bounds__(kScanWG) void scan_local(const uint32_t *in, uint64
     const uint64_t i = base + (uint64_t)threadIdx.x * kScanPer + j;
     if (i < n) out[i] = run;
     run += v[j];
+  }
+  if (RAW && blockIdx.x == nb - 1 && threadIdx.x == kScanWG - 1) {
+    bsum[nb] = run;
+    if (total_out) *total_out = run;
   }
 }
 
@@ -346,7 +371,7 @@ __global__ __launch_bounds__(64) void radix_scatter_tiles(TileSrc src, const uin
 // chunk's blocks before b.  Every access walks rows, 64 lanes over
 // consecutive digits.
 constexpr uint32_t kDigitChunk = 32;
-constexpr uint32_t kDigitWaves = 16;  // waves of digit_chunk_starts, one block per 64 digits
+constexpr uint32_t kDigitWaves = 4;  // waves of digit_chunk_starts, one block per 64 digits
 
 __global__ __launch_bounds__(256) void digit_chunk_sums(const uint32_t *__restrict__ h, uint64_t nblk, uint32_t nd,
                                                         uint32_t *__restrict__ csum) {
@@ -500,8 +525,13 @@ hipError_t launch_exclusive_scan(const uint32_t *in, uint64_t n, uint64_t *out, 
                                  hipStream_t s) {
   const uint64_t nb = (n + kScanBlock - 1) / kScanBlock;
   if (nb > 0) hipLaunchKernelGGL(scan_block_sums, dim3((uint32_t)nb), dim3(kScanWG), 0, s, in, n, tmp);
-  hipLaunchKernelGGL(scan_sums_single, dim3(1), dim3(1024), 0, s, tmp, nb, total_dev);
-  if (nb > 0) hipLaunchKernelGGL(scan_local, dim3((uint32_t)nb), dim3(kScanWG), 0, s, in, n, tmp, out);
+  if (nb > 0 && nb <= (uint64_t)kScanWG) {
+    hipLaunchKernelGGL((scan_local<true>), dim3((uint32_t)nb), dim3(kScanWG), 0, s, in, n, tmp, nb, out, total_dev);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(scan_sums_single, dim3(1), dim3(kScanWG), 0, s, tmp, nb, total_dev);
+  if (nb > 0)
+    hipLaunchKernelGGL((scan_local<false>), dim3((uint32_t)nb), dim3(kScanWG), 0, s, in, n, tmp, nb, out, nullptr);
   return hipGetLastError();
 }
 
