@@ -210,9 +210,11 @@ rk_status rk_scan_dump(rk_ctx *ctx, const uint8_t *text_dev, uint64_t n, uint32_
                        uint64_t stride, uint64_t *out_dev, uint64_t cap, int kernel, rk_stream s);
 
 /* Read-bandwidth ceiling for the scan's roofline: reads data_dev[0..n) once
- * with coalesced 16-byte loads (grid workgroups of 256 threads, grid-stride)
- * and writes one XOR-fold word per workgroup to out_dev[0..grid).  data_dev
- * 16-byte aligned, n a multiple of 16.  Timed by RK_OPT_PROFILE as kernel 4. */
+ * the way the scans load their tiles (non-temporal 16-byte loads straight into
+ * LDS, 1 KiB per wave load, grid workgroups of 256 threads, grid-stride) and
+ * writes the XOR fold of each workgroup's words to out_dev[0..grid).
+ * data_dev 16-byte aligned, n a multiple of 16.  Timed by RK_OPT_PROFILE as
+ * kernel 4. */
 rk_status rk_stream_read(rk_ctx *ctx, const void *data_dev, uint64_t n, uint32_t *out_dev, uint32_t grid,
                          rk_stream s);
 

@@ -729,27 +729,67 @@ void prepare_scan_kernels() {
 // Reads every 16-byte block of data[0..n) once (the scan's load width, fully
 // coalesced, grid-stride) and folds it into one word per workgroup so that
 // nothing is optimised away: the read-bandwidth ceiling the scan is held to.
-__global__ __launch_bounds__(256) void stream_read_kernel(const uint4 *data, uint64_t nblk, uint32_t *out) {
-  uint32_t acc = 0;
-  const uint64_t stride = (uint64_t)gridDim.x * 256u;
-  uint64_t i = (uint64_t)blockIdx.x * 256u + threadIdx.x;
-  for (; i + 3 * stride < nblk; i += 4 * stride) {
-    const uint4 a = data[i], b = data[i + stride], c = data[i + 2 * stride], d = data[i + 3 * stride];
-    acc ^= a.x ^ a.y ^ a.z ^ a.w ^ b.x ^ b.y ^ b.z ^ b.w ^ c.x ^ c.y ^ c.z ^ c.w ^ d.x ^ d.y ^ d.z ^ d.w;
+// Each wave streams 1 KiB chunks (gw, gw + TW, ...; TW waves in the grid)
+// into a private LDS ring of two sets of 8 slots with non-temporal LDS-DMA
+// loads, the way the scans load their tiles: a batch of 8 is issued, then the
+// previous batch is waited for and XOR-folded from LDS (every byte is read).
+// Tail bytes (n % 1024) are folded by the first workgroup's first wave.
+__device__ __forceinline__ uint32_t sr_lds(const void *p) {
+  return (uint32_t)(uintptr_t)(__attribute__((address_space(3))) const uint8_t *)p;
+}
+
+__device__ __forceinline__ void sr_dma(const void *g, uint32_t m0) {
+  __asm__ volatile("s_nop 0\n\tglobal_load_lds_dwordx4 %0, off nt" ::"v"(g), "{m0}"(m0) : "memory");
+}
+
+__global__ __launch_bounds__(256) void stream_read_kernel(const uint8_t *data, uint64_t n, uint32_t *out) {
+  __shared__ __attribute__((aligned(16))) uint8_t ring[4][2][8][1024];
+  const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint64_t nchunks = n / 1024, gw = (uint64_t)blockIdx.x * 4 + w, tw = (uint64_t)gridDim.x * 4;
+  uint32_t acc = 0, par = 0, prev = 0;
+  for (uint64_t c0 = gw; c0 < nchunks; c0 += 8 * tw) {
+    // the previous batch's reads of the set about to be refilled are done
+    __asm__ volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    uint32_t cnt = 0;
+#pragma unroll
+    for (uint32_t j = 0; j < 8; ++j) {
+      const uint64_t c = c0 + j * tw;
+      if (c < nchunks) {
+        sr_dma(data + c * 1024 + 16 * lane, __builtin_amdgcn_readfirstlane(sr_lds(&ring[w][par][j][0])));
+        ++cnt;
+      }
+    }
+    if (cnt == 8)
+      __builtin_amdgcn_s_waitcnt(0x0F78);  // vmcnt(8): the previous batch has landed
+    else
+      __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+    __asm__ volatile("" ::: "memory");
+    for (uint32_t j = 0; j < prev; ++j) {
+      const uint4 v = *(const uint4 *)&ring[w][par ^ 1][j][16 * lane];
+      acc ^= v.x ^ v.y ^ v.z ^ v.w;
+    }
+    prev = cnt;
+    par ^= 1;
   }
-  for (; i < nblk; i += stride) {
-    const uint4 a = data[i];
-    acc ^= a.x ^ a.y ^ a.z ^ a.w;
+  __builtin_amdgcn_s_waitcnt(0x0F70);
+  __asm__ volatile("" ::: "memory");
+  for (uint32_t j = 0; j < prev; ++j) {
+    const uint4 v = *(const uint4 *)&ring[w][par ^ 1][j][16 * lane];
+    acc ^= v.x ^ v.y ^ v.z ^ v.w;
+  }
+  if (blockIdx.x == 0 && w == 0 && nchunks * 1024 + 16 * lane < n) {
+    const uint4 v = *(const uint4 *)(data + nchunks * 1024 + 16 * lane);
+    acc ^= v.x ^ v.y ^ v.z ^ v.w;
   }
   for (int d = 32; d >= 1; d >>= 1) acc ^= __shfl_xor(acc, d, 64);
   __shared__ uint32_t red[4];
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  if (lane == 0) red[w] = acc;
   __syncthreads();
   if (threadIdx.x == 0) out[blockIdx.x] = red[0] ^ red[1] ^ red[2] ^ red[3];
 }
 
 hipError_t launch_stream_read(const void *data, uint64_t n, uint32_t *out, uint32_t grid, hipStream_t s) {
-  hipLaunchKernelGGL(stream_read_kernel, dim3(grid), dim3(256), 0, s, (const uint4 *)data, n / 16, out);
+  hipLaunchKernelGGL(stream_read_kernel, dim3(grid), dim3(256), 0, s, (const uint8_t *)data, n, out);
   return hipGetLastError();
 }
 

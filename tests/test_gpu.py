@@ -397,6 +397,27 @@ def test_window_hashes_match_oracle(ctx, rk):
     assert (bad.astype(np.uint64) == np.uint64(2**64 - 1)).all()
 
 
+def test_stream_read_folds_every_word_once(ctx, rk):
+    """The roofline's read kernel: the XOR of its per-workgroup folds is the
+    XOR of every 4-byte word of the buffer (a chunk read twice or skipped
+    would change it), for grids that leave waves idle, bodies that are not a
+    whole number of batches and a tail that is not a whole 1 KiB chunk."""
+    import ctypes
+    g = rkgen.rng(55, 0)
+    for n in (16, 1008, 1024, (1 << 20) + 528, 8 * 1024 * 37 + 16 * 5):
+        data = np.frombuffer(g.bytes(n), np.uint8).copy()
+        want = int(np.bitwise_xor.reduce(data.view(np.uint32)))
+        t = dev(data)
+        for grid in (1, 7, 64, 300):
+            out = torch.zeros(grid, dtype=torch.int32, device="cuda:0")
+            st = ctx.lib.rk_stream_read(ctx.h, ctypes.c_void_p(t.data_ptr()), n, ctypes.c_void_p(out.data_ptr()),
+                                        grid, None)
+            assert st == 0
+            torch.cuda.synchronize()
+            got = int(np.bitwise_xor.reduce(out.cpu().numpy().view(np.uint32)))
+            assert got == want, (n, grid)
+
+
 @pytest.mark.parametrize("mode", MODES)
 def test_slab_overflow_rescan(ctx, rk, mode):
     """A one-slot staging slab forces every tile with hits through the rescan."""
