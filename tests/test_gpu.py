@@ -397,6 +397,30 @@ def test_window_hashes_match_oracle(ctx, rk):
     assert (bad.astype(np.uint64) == np.uint64(2**64 - 1)).all()
 
 
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("k", [1, 3])
+def test_sparse_compaction_clustered_hits(ctx, rk, mode, k):
+    """Fewer hits than tiles, so the collect compacts a tile per lane: most
+    tiles hold 0-2 hits (a lane copies them), a cluster of 20 plants puts
+    more than eight in one tile (the wave copies it), and a dense cluster
+    overflows its tile's staging slab (rescanned, not compacted)."""
+    g = rkgen.rng(56, k)
+    n = (64 if k == 1 else 128) << 20
+    text = rkgen.iid_text(g, n, np.frombuffer(b"ACGT", np.uint8))
+    p0 = np.frombuffer(b"ACGTTGCAAC", np.uint8)
+    # more plants in one tile than its slab holds: W/64 records for a single
+    # pattern (up to 528 at W = 33,792), W/16 for a set (up to 2,112)
+    span, step = (16384, 20) if k == 1 else (24576, 10)
+    for o in range(1 << 20, (1 << 20) + span - 10, step):
+        text[o:o + 10] = p0
+    for o in range(9 << 20, (9 << 20) + 20 * 64, 64):
+        text[o:o + 10] = p0
+    pats = [p0.tobytes()] + [bytes(g.choice(np.frombuffer(b"ACGT", np.uint8), 10)) for _ in range(k - 1)]
+    ref = oracle.search(text, pats, threads=4)
+    assert int(ref[0][-1]) < n // (256 * 132)  # fewer hits than tiles, whatever the geometry
+    assert_same(run(ctx, rk, text, pats, mode), ref, "clustered k=%d %s" % (k, mode))
+
+
 def test_stream_read_folds_every_word_once(ctx, rk):
     """The roofline's read kernel: the XOR of its per-workgroup folds is the
     XOR of every 4-byte word of the buffer (a chunk read twice or skipped
