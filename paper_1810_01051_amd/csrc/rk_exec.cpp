@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cstring>
 #include <map>
 #include <new>
@@ -397,6 +398,26 @@ static void base_params(const rk_plan *plan, const Layout &L, uint32_t pi, uint8
   p.grab = 1;
 }
 
+// Instance descriptors of a single-text plan's text (one per virtual
+// instance) into the scratch; nothing for batch plans, whose descriptors
+// live in the plan.
+static hipError_t upload_insts(const rk_plan *plan, const Layout &L, uint8_t *sc, const uint8_t *text, uint64_t n,
+                               hipStream_t s) {
+  if (plan->batch || plan->vinsts.empty()) return hipSuccess;
+  std::vector<InstDesc> d(plan->vinsts.size());
+  for (size_t i = 0; i < d.size(); ++i) {
+    memset(&d[i], 0, sizeof(InstDesc));
+    d[i].text = text;
+    d[i].n = n;
+    d[i].tile_base = L.T1 * i;
+    d[i].ntiles = L.T1;
+    d[i].img_off = plan->vinsts[i].img_off;
+    d[i].lds_bytes = plan->vinsts[i].lds_bytes;
+  }
+  // hipMemcpyAsync from pageable memory stages the data before returning
+  return hipMemcpyAsync(sc + L.inst, d.data(), d.size() * sizeof(InstDesc), hipMemcpyHostToDevice, s);
+}
+
 rk_status count_enqueue(rk_ctx *ctx, const rk_plan *plan, const uint8_t *text, uint64_t n, void *scratch,
                         uint64_t scratch_bytes, uint64_t *counts, hipStream_t s) {
   if (plan->device != ctx->device) return set_err(ctx, RK_EINVAL, "plan belongs to another device");
@@ -415,21 +436,13 @@ rk_status count_enqueue(rk_ctx *ctx, const rk_plan *plan, const uint8_t *text, u
   if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, RK_EDEVICE, "hipSetDevice failed");
   uint8_t *sc = (uint8_t *)scratch;
   hipError_t e;
-  if (!plan->batch && !plan->vinsts.empty()) {
-    // instance descriptors of this text (one per virtual instance)
-    std::vector<InstDesc> d(plan->vinsts.size());
-    for (size_t i = 0; i < d.size(); ++i) {
-      memset(&d[i], 0, sizeof(InstDesc));
-      d[i].text = text;
-      d[i].n = n;
-      d[i].tile_base = L.T1 * i;
-      d[i].ntiles = L.T1;
-      d[i].img_off = plan->vinsts[i].img_off;
-      d[i].lds_bytes = plan->vinsts[i].lds_bytes;
-    }
-    const size_t bytes = d.size() * sizeof(InstDesc);
-    // hipMemcpyAsync from pageable memory stages the data before returning
-    e = hipMemcpyAsync(sc + L.inst, d.data(), bytes, hipMemcpyHostToDevice, s);
+  const bool use_queue = ctx->queue == 1 || (ctx->queue == -1 && plan->batch);
+  // one text, one bucket with register targets: the single-bucket kernel,
+  // which takes the text itself (the general kernel reads it through the
+  // instance descriptors, uploaded here for it and by a rescan)
+  const bool list = plan->list1 && !use_queue;
+  if (!list) {
+    e = upload_insts(plan, L, sc, text, n, s);
     if (e != hipSuccess) return hip_err(ctx, e, "instance upload");
   }
   e = launch_fill_u32((uint32_t *)(sc + L.ctr), 64, 0u, s);
@@ -439,10 +452,8 @@ rk_status count_enqueue(rk_ctx *ctx, const rk_plan *plan, const uint8_t *text, u
     if (e != hipSuccess) return hip_err(ctx, e, "per-pattern count reset");
   }
   if (L.T == 0) return RK_OK;
-  const bool use_queue = ctx->queue == 1 || (ctx->queue == -1 && plan->batch);
   int slot;
-  if (plan->list1 && !use_queue) {
-    // one text, one bucket with register targets: the single-bucket kernel
+  if (list) {
     const PartRun &r = L.parts[0];
     ListParams lp;
     memset(&lp, 0, sizeof lp);
@@ -511,7 +522,19 @@ rk_status count_enqueue(rk_ctx *ctx, const rk_plan *plan, const uint8_t *text, u
 rk_status count_finish(rk_ctx *ctx, const rk_plan *plan, void *scratch, hipStream_t s, uint64_t *total) {
   hipError_t e = hipMemcpyAsync(ctx->pinned, scratch, 64, hipMemcpyDeviceToHost, s);
   if (e != hipSuccess) return hip_err(ctx, e, "total readback");
-  e = hipStreamSynchronize(s);
+  // A count pass of a few GiB takes about a millisecond, less than a blocking
+  // wait adds in wake-up latency: the stream is polled for up to kSpinUs,
+  // then waited for.
+  constexpr int64_t kSpinUs = 4000;
+  const auto t0 = std::chrono::steady_clock::now();
+  for (;;) {
+    e = hipStreamQuery(s);
+    if (e != hipErrorNotReady) break;
+    if (std::chrono::steady_clock::now() - t0 > std::chrono::microseconds(kSpinUs)) {
+      e = hipStreamSynchronize(s);
+      break;
+    }
+  }
   if (e != hipSuccess) return hip_err(ctx, e, "scan");
   *total = ctx->pinned[0];
   const uint32_t ovf = ovf_total(ctx->pinned);
@@ -526,7 +549,6 @@ rk_status count_finish(rk_ctx *ctx, const rk_plan *plan, void *scratch, hipStrea
 rk_status collect_enqueue(rk_ctx *ctx, const rk_plan *plan, const uint8_t *text, uint64_t n, void *scratch,
                           uint64_t scratch_bytes, void *work, uint64_t work_bytes, uint64_t *offsets,
                           uint64_t *positions, uint64_t capacity, hipStream_t s) {
-  (void)text;
   if (!offsets) return set_err(ctx, RK_EINVAL, "null offsets");
   Layout L;
   rk_status st = make_layout(ctx, plan, n, L);
@@ -548,13 +570,14 @@ rk_status collect_enqueue(rk_ctx *ctx, const rk_plan *plan, const uint8_t *text,
     if (e != hipSuccess) return hip_err(ctx, e, "total readback");
     total = ctx->pinned[0];
   }
-  return collect_enqueue_known(ctx, plan, n, scratch, scratch_bytes, work, work_bytes, offsets, positions, capacity,
+  return collect_enqueue_known(ctx, plan, text, n, scratch, scratch_bytes, work, work_bytes, offsets, positions, capacity,
                                total, overflow, s);
 }
 
 // Collect with the count pass's total and overflowed-tile count given by the
 // caller (overflow = all ones: unknown, the rescan is launched).
-rk_status collect_enqueue_known(rk_ctx *ctx, const rk_plan *plan, uint64_t n, void *scratch, uint64_t scratch_bytes,
+rk_status collect_enqueue_known(rk_ctx *ctx, const rk_plan *plan, const uint8_t *text, uint64_t n, void *scratch,
+                                uint64_t scratch_bytes,
                                 void *work, uint64_t work_bytes, uint64_t *offsets, uint64_t *positions,
                                 uint64_t capacity, uint64_t total, uint32_t overflow, hipStream_t s) {
   Layout L;
@@ -635,6 +658,13 @@ rk_status collect_enqueue_known(rk_ctx *ctx, const rk_plan *plan, uint64_t n, vo
   // rescan of tiles whose hits did not fit their slab, part by part (each
   // part's count read on the device; skipped when the count pass reported none)
   if (overflow != 0) {
+    // the rescan runs the general kernel, which reads the text through the
+    // instance descriptors (a single-bucket count did not upload them)
+    if (!plan->batch && !plan->vinsts.empty()) {
+      if (!text) return set_err(ctx, RK_EINVAL, "the rescan of overflowed tiles needs text_dev");
+      e = upload_insts(plan, L, sc, text, n, s);
+      if (e != hipSuccess) return hip_err(ctx, e, "instance upload");
+    }
     for (uint32_t pi = 0; pi < plan->parts.size(); ++pi) {
       const Part &pt = plan->parts[pi];
       const PartRun &r = L.parts[pi];

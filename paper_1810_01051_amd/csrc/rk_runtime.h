@@ -164,9 +164,12 @@ rk_status count_finish(rk_ctx *ctx, const rk_plan *plan, void *scratch, hipStrea
 rk_status collect_enqueue(rk_ctx *ctx, const rk_plan *plan, const uint8_t *text, uint64_t n, void *scratch,
                           uint64_t scratch_bytes, void *work, uint64_t work_bytes, uint64_t *offsets,
                           uint64_t *positions, uint64_t capacity, hipStream_t s);
-rk_status collect_enqueue_known(rk_ctx *ctx, const rk_plan *plan, uint64_t n, void *scratch, uint64_t scratch_bytes,
-                                void *work, uint64_t work_bytes, uint64_t *offsets, uint64_t *positions,
-                                uint64_t capacity, uint64_t total, uint32_t overflow, hipStream_t s);
+// text: the counted text (single-text plans: a rescan of overflowed tiles
+// reads it; batch plans: null)
+rk_status collect_enqueue_known(rk_ctx *ctx, const rk_plan *plan, const uint8_t *text, uint64_t n, void *scratch,
+                                uint64_t scratch_bytes, void *work, uint64_t work_bytes, uint64_t *offsets,
+                                uint64_t *positions, uint64_t capacity, uint64_t total, uint32_t overflow,
+                                hipStream_t s);
 rk_status plan_build_host(rk_ctx *ctx, const rk_instance *inst, uint32_t count, int mode, bool batch, rk_plan *P,
                           std::vector<uint8_t> &blob, std::vector<InstDesc> &descs, std::vector<uint64_t> &items);
 void plan_sizes(const std::vector<uint8_t> &blob, const std::vector<InstDesc> &descs, const std::vector<uint64_t> &items,

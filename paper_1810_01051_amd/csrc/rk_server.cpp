@@ -509,8 +509,9 @@ static bool try_collect(rk_server *S, Slot &sl, std::unique_lock<std::mutex> &lk
     if (st == RK_OK)
       st = run_maybe_graph(S, sl, &sl.gcollect, [&]() -> rk_status {
         S->ctx->slab_cap = sl.slab_cap;  // the layout of this step's count pass
-        rk_status s2 = collect_enqueue_known(S->ctx, &sl.plan, 0, sl.scratch, sl.scratch_cap, work, work_b, doff,
-                                             dpos, std::max<uint64_t>(sl.total, 1), sl.total, sl.ovf, sl.stream);
+        rk_status s2 = collect_enqueue_known(S->ctx, &sl.plan, nullptr, 0, sl.scratch, sl.scratch_cap, work, work_b,
+                                             doff, dpos, std::max<uint64_t>(sl.total, 1), sl.total, sl.ovf,
+                                             sl.stream);
         if (s2 != RK_OK) return s2;
         hipError_t e2 = hipMemcpyAsync(sl.hres, doff, (uint64_t)(k + 1) * 8, hipMemcpyDeviceToHost, sl.stream);
         return e2 == hipSuccess ? RK_OK : hip_err(S->ctx, e2, "offset copy");
