@@ -10,7 +10,7 @@
 // next piece and are dropped; the rest are shifted by i L and appended, so the
 // concatenation per pattern stays ascending.
 //
-// Overlap: piece i + 1 is staged into pinned host memory (several threads
+// Overlap: piece i + 1 is staged into pinned host memory (up to 16 threads
 // copy, or read from the file) while piece i is copied to the device and
 // searched; the host-to-device copy of piece i + 1 runs on a copy stream
 // while the collect of piece i runs on the search stream.  The link
@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <fcntl.h>
+#include <sched.h>
 #include <unistd.h>
 
 #include <algorithm>
@@ -99,6 +100,18 @@ static bool stage(const Source &src, uint64_t off, uint64_t len, uint8_t *dst, i
   return true;
 }
 
+// Threads that stage a piece: the CPUs this process may run on, at most 16.
+// Staging from pageable memory is a host memcpy that one thread runs at a
+// fraction of the host's memory bandwidth; with 8 threads it took longer than
+// the host-to-device copy of the same piece.
+static int staging_threads() {
+  cpu_set_t set;
+  int n = 0;
+  if (sched_getaffinity(0, sizeof set, &set) == 0) n = CPU_COUNT(&set);
+  if (n <= 0) n = (int)std::thread::hardware_concurrency();
+  return std::max(1, std::min(16, n));
+}
+
 struct PieceOut {
   std::vector<uint64_t> off;  // k + 1, after dropping positions >= L
   std::vector<uint64_t> pos;  // shifted to text positions
@@ -122,7 +135,7 @@ static rk_status run_pieces(rk_ctx *ctx, const rk_plan *plan, const Source &src,
   hipEvent_t copied[2] = {nullptr, nullptr}, used[2] = {nullptr, nullptr};
   rk_status st = RK_OK;
   std::vector<PieceOut> pieces;
-  const int threads = (int)std::max(1u, std::min(8u, std::thread::hardware_concurrency()));
+  const int threads = staging_threads();
   auto fail = [&](hipError_t e, const char *what) { return hip_err(ctx, e, what); };
   hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&ss, hipStreamNonBlocking);
