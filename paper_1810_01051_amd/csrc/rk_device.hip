@@ -249,18 +249,25 @@ __global__ __launch_bounds__(64) void radix_scatter(const uint64_t *in, uint64_t
   __syncthreads();
   const uint32_t lane = threadIdx.x;
   const uint64_t me = 1ull << lane, lt_mask = me - 1ull;
-  const uint64_t base = (uint64_t)blockIdx.x * BLK;
-  for (int j = 0; j < BLK; j += 64 * kRadixR) {
-    uint64_t recs[kRadixR];
+  // rounds of 64 * kRadixR records; the next round's loads are issued before
+  // the current one is ranked, all unconditional (indices clamped to the
+  // block's last record, the lanes past it skipped when ranking)
+  const uint64_t base = (uint64_t)blockIdx.x * BLK, end = min(base + BLK, n);
+  auto load_round = [&](uint64_t j, uint64_t (&r)[kRadixR]) __attribute__((always_inline)) {
+#pragma unroll
+    for (int u = 0; u < kRadixR; ++u) r[u] = in[min(j + (uint64_t)u * 64u + lane, end - 1)];
+  };
+  uint64_t cur[kRadixR];
+  load_round(base, cur);
+  for (uint64_t j = base;; j += 64u * kRadixR) {
+    // (a block of one round has no next one: 8-bit passes)
+    const bool more = BLK > 64 * kRadixR && j + 64u * kRadixR < end;
+    uint64_t nxt[kRadixR];
+    if constexpr (BLK > 64 * kRadixR) load_round(more ? j + 64u * kRadixR : j, nxt);
 #pragma unroll
     for (int u = 0; u < kRadixR; ++u) {
-      const uint64_t i = base + j + u * 64 + lane;
-      recs[u] = i < n ? in[i] : ~0ull;
-    }
-#pragma unroll
-    for (int u = 0; u < kRadixR; ++u) {
-      const uint64_t rec = recs[u];
-      if (rec == ~0ull) continue;
+      if (j + (uint64_t)u * 64u + lane >= end) continue;
+      const uint64_t rec = cur[u];
       const uint32_t dg = (uint32_t)(rec >> shift) & (ND - 1u);
       atomicOr(&grp[dg], (unsigned long long)me);
       const uint64_t peers = grp[dg];
@@ -270,6 +277,11 @@ __global__ __launch_bounds__(64) void radix_scatter(const uint64_t *in, uint64_t
         run[dg] = at + __builtin_popcountll(peers);
         grp[dg] = 0;
       }
+    }
+    if (!more) break;
+    if constexpr (BLK > 64 * kRadixR) {
+#pragma unroll
+      for (int u = 0; u < kRadixR; ++u) cur[u] = nxt[u];
     }
   }
 }
@@ -316,7 +328,17 @@ __global__ __launch_bounds__(256) void radix_hist_tiles(TileSrc src, uint32_t *g
 }
 
 // Positions of the records to their final place (the last and only pass),
-// ranked as in radix_scatter.
+// ranked as in radix_scatter.  The block's tiles are one stream of rounds of
+// 64 * kRadixR records.  A round's loads are unconditional (indices clamped
+// to the tile's last record; the lanes past it are skipped when ranking), so
+// that the compiler can count them, and the next round's loads are issued
+// before the current round is ranked: a wave then waits for its loads once
+// per two rounds' latency instead of draining before every round.
+__device__ __forceinline__ void tiles_load_round(const uint64_t *in, uint32_t j, uint32_t c, uint64_t (&r)[kRadixR]) {
+#pragma unroll
+  for (int u = 0; u < kRadixR; ++u) r[u] = in[min(j + (uint32_t)u * 64u + threadIdx.x, c - 1u)];
+}
+
 template <int DB>
 __global__ __launch_bounds__(64) void radix_scatter_tiles(TileSrc src, const uint64_t *goff, uint64_t nblk,
                                                           uint64_t *out) {
@@ -333,31 +355,54 @@ __global__ __launch_bounds__(64) void radix_scatter_tiles(TileSrc src, const uin
   const uint64_t me = 1ull << lane, lt_mask = me - 1ull;
   const uint64_t t0 = src.tile0 + (uint64_t)blockIdx.x * src.G;
   const uint64_t t1 = min(t0 + src.G, src.tile0 + src.ntiles);
-  for (uint64_t t = t0; t < t1; ++t) {
-    uint32_t c;
-    const uint64_t *in = tile_records(src, t, c);
-    for (uint32_t j = 0; j < c; j += 64 * kRadixR) {
-      uint64_t recs[kRadixR];
-#pragma unroll
-      for (int u = 0; u < kRadixR; ++u) {
-        const uint32_t i = j + u * 64 + lane;
-        recs[u] = i < c ? in[i] : ~0ull;
-      }
-#pragma unroll
-      for (int u = 0; u < kRadixR; ++u) {
-        const uint64_t rec = recs[u];
-        if (rec == ~0ull) continue;
-        const uint32_t dg = (uint32_t)(rec >> kPosBits) & (ND - 1u);
-        atomicOr(&grp[dg], (unsigned long long)me);
-        const uint64_t peers = grp[dg];
-        const uint64_t at = run[dg];
-        out[at + __builtin_popcountll(peers & lt_mask)] = rec & kPosMask;
-        if ((peers >> lane) == 1ull) {
-          run[dg] = at + __builtin_popcountll(peers);
-          grp[dg] = 0;
-        }
+  // the first tile holding records (the round is (t, j): records j.. of tile t)
+  uint64_t t = t0;
+  uint32_t c = 0, j = 0;
+  const uint64_t *in = nullptr;
+  for (; t < t1; ++t) {
+    in = tile_records(src, t, c);
+    if (c) break;
+  }
+  if (t >= t1) return;
+  uint64_t cur[kRadixR];
+  tiles_load_round(in, j, c, cur);
+  for (;;) {
+    // the next round: further in this tile, else the next tile with records
+    uint64_t nt = t;
+    uint32_t nj = j + 64u * kRadixR, nc = c;
+    const uint64_t *nin = in;
+    if (nj >= c) {
+      nj = 0;
+      for (++nt; nt < t1; ++nt) {
+        nin = tile_records(src, nt, nc);
+        if (nc) break;
       }
     }
+    const bool more = nt < t1;
+    uint64_t nxt[kRadixR];
+    // after the last round this reloads the current one (not used)
+    tiles_load_round(more ? nin : in, more ? nj : j, more ? nc : c, nxt);
+#pragma unroll
+    for (int u = 0; u < kRadixR; ++u) {
+      if (j + (uint32_t)u * 64u + lane >= c) continue;
+      const uint64_t rec = cur[u];
+      const uint32_t dg = (uint32_t)(rec >> kPosBits) & (ND - 1u);
+      atomicOr(&grp[dg], (unsigned long long)me);
+      const uint64_t peers = grp[dg];
+      const uint64_t at = run[dg];
+      out[at + __builtin_popcountll(peers & lt_mask)] = rec & kPosMask;
+      if ((peers >> lane) == 1ull) {
+        run[dg] = at + __builtin_popcountll(peers);
+        grp[dg] = 0;
+      }
+    }
+    if (!more) break;
+#pragma unroll
+    for (int u = 0; u < kRadixR; ++u) cur[u] = nxt[u];
+    t = nt;
+    j = nj;
+    c = nc;
+    in = nin;
   }
 }
 
