@@ -580,6 +580,19 @@ hipError_t launch_exclusive_scan(const uint32_t *in, uint64_t n, uint64_t *out, 
   return hipGetLastError();
 }
 
+hipError_t launch_exclusive_scan_summed(const uint32_t *in, uint64_t n, uint64_t *out, uint64_t *bsum, hipStream_t s) {
+  static_assert(kScanBlock == (1 << kTileSumLog2), "the count pass sums the scan's blocks");
+  const uint64_t nb = (n + kScanBlock - 1) / kScanBlock;
+  if (nb == 0) return hipSuccess;
+  if (nb <= (uint64_t)kScanWG) {
+    hipLaunchKernelGGL((scan_local<true>), dim3((uint32_t)nb), dim3(kScanWG), 0, s, in, n, bsum, nb, out, nullptr);
+  } else {
+    hipLaunchKernelGGL(scan_sums_single, dim3(1), dim3(kScanWG), 0, s, bsum, nb, nullptr);
+    hipLaunchKernelGGL((scan_local<false>), dim3((uint32_t)nb), dim3(kScanWG), 0, s, in, n, bsum, nb, out, nullptr);
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_compact(const uint32_t *counts, const uint64_t *offs, uint64_t ntiles, const uint64_t *slabs,
                           uint32_t slab_cap, uint64_t *out, bool sparse, uint64_t *offsets1, uint64_t total,
                           hipStream_t s) {

@@ -298,12 +298,15 @@ rk_status make_layout(rk_ctx *ctx, const rk_plan *plan, uint64_t n, Layout &L) {
     o = align_up(o + bytes, 256);
     return r;
   };
-  L.ctr = take(256);
+  // the counters and the tiles' block sums are one region, cleared by one
+  // fill before every count pass
+  L.nbsum = (L.T + (1u << kTileSumLog2) - 1) / (1u << kTileSumLog2) + 1;
+  L.ctr = take(256 + L.nbsum * 8);
+  L.bsum = L.ctr + 256;
   L.inst = take(plan->batch ? 0 : plan->vinsts.size() * sizeof(InstDesc));
   L.counts = take(L.T * 4);
   L.offsets = take(L.T * 8);
   L.ovf = take(L.T * 8);
-  L.tmp = take(scan_tmp_words(L.T) * 8);
   for (PartRun &r : L.parts) r.slabs = take(r.ntiles * (uint64_t)r.S * 8);
   L.total = o;
   return RK_OK;
@@ -393,6 +396,7 @@ static void base_params(const rk_plan *plan, const Layout &L, uint32_t pi, uint8
   p.slab_cap = r.S;
   p.tile0 = r.tile0;
   p.total = (unsigned long long *)(sc + L.ctr);
+  p.blk_sums = (unsigned long long *)(sc + L.bsum);
   p.ovf_count = (uint32_t *)(sc + L.ctr + kCtrOvf) + pi;
   p.ovf_list = (uint64_t *)(sc + L.ovf) + r.tile0;  // the part's own overflow list
   p.grab = 1;
@@ -445,7 +449,7 @@ rk_status count_enqueue(rk_ctx *ctx, const rk_plan *plan, const uint8_t *text, u
     e = upload_insts(plan, L, sc, text, n, s);
     if (e != hipSuccess) return hip_err(ctx, e, "instance upload");
   }
-  e = launch_fill_u32((uint32_t *)(sc + L.ctr), 64, 0u, s);
+  e = launch_fill_u32((uint32_t *)(sc + L.ctr), 64 + 2 * L.nbsum, 0u, s);
   if (e != hipSuccess) return hip_err(ctx, e, "counter reset");
   if (counts) {
     e = launch_fill_u32((uint32_t *)counts, 2ull * plan->k_total, 0u, s);
@@ -468,6 +472,7 @@ rk_status count_enqueue(rk_ctx *ctx, const rk_plan *plan, const uint8_t *text, u
     lp.tile_counts = (uint32_t *)(sc + L.counts);
     lp.out = (uint64_t *)(sc + r.slabs);
     lp.total = (unsigned long long *)(sc + L.ctr);
+    lp.blk_sums = (unsigned long long *)(sc + L.bsum);
     lp.ovf_count = (uint32_t *)(sc + L.ctr + kCtrOvf);
     lp.ovf_list = (uint64_t *)(sc + L.ovf);
     lp.pid_counts = (unsigned long long *)counts;
@@ -608,7 +613,7 @@ rk_status collect_enqueue_known(rk_ctx *ctx, const rk_plan *plan, const uint8_t 
     return hip_err_or_ok(ctx, prof_end(ctx, s, slot));
   }
   uint64_t *tile_off = (uint64_t *)(sc + L.offsets);
-  e = launch_exclusive_scan((const uint32_t *)(sc + L.counts), L.T, tile_off, (uint64_t *)(sc + L.tmp), nullptr, s);
+  e = launch_exclusive_scan_summed((const uint32_t *)(sc + L.counts), L.T, tile_off, (uint64_t *)(sc + L.bsum), s);
   if (e != hipSuccess) return hip_err(ctx, e, "tile scan");
   WorkLayout WL = work_layout(total, k);
   uint64_t *target = k == 1 ? positions : (uint64_t *)((uint8_t *)work + WL.a);

@@ -122,6 +122,11 @@ struct InstDesc {
 };
 static_assert(sizeof(InstDesc) == 48, "instance descriptor is 48 bytes");
 
+// The count pass adds each tile's hits to its block of 2^kTileSumLog2 tiles
+// (the blocks of the collect's prefix sum of the tile counts, which then
+// starts from these sums).
+constexpr uint32_t kTileSumLog2 = 12;
+
 // Kernel parameters of the scan (passed by value).
 struct ScanParams {
   const InstDesc *inst;
@@ -146,6 +151,7 @@ struct ScanParams {
   uint64_t dump_cap;
   unsigned long long *pid_counts; // count mode, optional: hits per global pattern id
   uint64_t tile0;             // count mode: global id of the first tile of out's slabs
+  unsigned long long *blk_sums; // count mode, optional: hits per 2^kTileSumLog2 global tiles
 };
 
 // Kernel parameters of the single-bucket scan (one text, one bucket whose set
@@ -168,6 +174,7 @@ struct ListParams {
   uint64_t dump_stride;
   uint64_t dump_cap;
   unsigned long long *pid_counts; // optional: hits per pattern id
+  unsigned long long *blk_sums; // optional: hits per 2^kTileSumLog2 tiles
 };
 
 // Host-side geometry table (workgroup size, windows per thread).

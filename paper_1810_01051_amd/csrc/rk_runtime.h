@@ -134,7 +134,8 @@ struct Layout {
   uint64_t T = 0;      // tiles over all parts
   uint64_t T1 = 0;     // tiles per virtual instance (single plans)
   std::vector<PartRun> parts;
-  uint64_t ctr = 0, inst = 0, counts = 0, offsets = 0, ovf = 0, tmp = 0, total = 0;
+  uint64_t ctr = 0, inst = 0, counts = 0, offsets = 0, ovf = 0, total = 0;
+  uint64_t bsum = 0, nbsum = 0;  // the tiles' block sums (u64, nbsum entries) right after the 64 counter words
 };
 constexpr uint32_t kCtrOvf = 8, kCtrQueue = 48;
 // Tiles that overflowed their slabs, summed over parts, from the first 64
@@ -205,6 +206,9 @@ hipError_t list_scan(int cfg, int fam, const ListParams *p, uint32_t grid, hipSt
 uint64_t scan_tmp_words(uint64_t n);
 hipError_t launch_exclusive_scan(const uint32_t *in, uint64_t n, uint64_t *out, uint64_t *tmp, uint64_t *total_dev,
                                  hipStream_t s);
+// the same scan when bsum already holds the sums of the counts' blocks of
+// 2^kTileSumLog2 (bsum: ceil(n / 2^kTileSumLog2) + 1 entries, overwritten)
+hipError_t launch_exclusive_scan_summed(const uint32_t *in, uint64_t n, uint64_t *out, uint64_t *bsum, hipStream_t s);
 // sparse: fewer hits than tiles (a lane per tile); offsets1: a single
 // pattern's offsets, written {0, total}, or null
 hipError_t launch_compact(const uint32_t *counts, const uint64_t *offs, uint64_t ntiles, const uint64_t *slabs,

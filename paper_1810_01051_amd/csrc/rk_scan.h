@@ -1343,7 +1343,10 @@ __global__ __launch_bounds__(WG) void scan_kernel(ScanParams p) {
 
     if (tid == 0 && !p.direct) {
       p.tile_counts[gt] = tile_hits;
-      if (tile_hits) atomicAdd(p.total, (unsigned long long)tile_hits);
+      if (tile_hits) {
+        atomicAdd(p.total, (unsigned long long)tile_hits);
+        if (p.blk_sums) atomicAdd(p.blk_sums + (gt >> kTileSumLog2), (unsigned long long)tile_hits);
+      }
       if (tile_hits > p.slab_cap) {
         const uint32_t o = atomicAdd(p.ovf_count, 1u);
         p.ovf_list[o] = gt;
@@ -1436,7 +1439,10 @@ __global__ __launch_bounds__(WG) void scan_list_kernel(ListParams p) {
     }
     if (tid == 0) {
       p.tile_counts[t] = tile_hits;
-      if (tile_hits) atomicAdd(p.total, (unsigned long long)tile_hits);
+      if (tile_hits) {
+        atomicAdd(p.total, (unsigned long long)tile_hits);
+        if (p.blk_sums) atomicAdd(p.blk_sums + (t >> kTileSumLog2), (unsigned long long)tile_hits);
+      }
       if (tile_hits > p.slab_cap) {
         const uint32_t o = atomicAdd(p.ovf_count, 1u);
         p.ovf_list[o] = t;
