@@ -421,6 +421,47 @@ def test_sparse_compaction_clustered_hits(ctx, rk, mode, k):
     assert_same(run(ctx, rk, text, pats, mode), ref, "clustered k=%d %s" % (k, mode))
 
 
+@pytest.mark.parametrize("k", [1, 2])
+def test_tile_offsets_beyond_256_sum_blocks(ctx, rk, k):
+    """A 10 GiB text in the 9,216-byte tile geometry has 1,165,085 tiles, more
+    than 256 blocks of 4,096: the collect then scans the count pass's block
+    sums in one workgroup before the per-block tile offsets.  The text is one
+    byte repeated with plants 64 bytes apart or more, so the positions are
+    known without the oracle."""
+    n = 10 << 30
+    assert (n + 9215) // 9216 > 256 * 4096
+    g = rkgen.rng(57, k)
+    pats = [b"xyzzy", b"qqq"][:k]
+    text = torch.full((n,), ord("a"), dtype=torch.uint8, device="cuda:0")
+    try:
+        want = []
+        for j, p in enumerate(pats):
+            # spread over the whole text, plus the first and the last windows
+            pos = np.unique(g.integers(0, n // 64 - 1, size=3000)) * 64 + 16 * j
+            pos = np.concatenate([[j * 8], pos, [n - len(p) - 32 * j]]).astype(np.int64)
+            pos = np.unique(pos)
+            idx = torch.from_numpy(pos).to("cuda:0")
+            for i, c in enumerate(p):
+                text[idx + i] = c
+            want.append(pos)
+        torch.cuda.synchronize()
+        ctx.set_option(rk._lib.RK_OPT_TILE_CFG, 3)
+        try:
+            plan = rk.Plan(ctx, pats, "screen")
+            off, got = plan.search(text)
+            torch.cuda.synchronize()
+            plan.close()
+        finally:
+            ctx.set_option(rk._lib.RK_OPT_TILE_CFG, -1)
+        off = off.cpu().numpy()
+        got = got.cpu().numpy()
+        for j in range(k):
+            assert got[off[j]:off[j + 1]].tolist() == want[j].tolist(), j
+    finally:
+        del text
+        torch.cuda.empty_cache()
+
+
 def test_stream_read_folds_every_word_once(ctx, rk):
     """The roofline's read kernel: the XOR of its per-workgroup folds is the
     XOR of every 4-byte word of the buffer (a chunk read twice or skipped
